@@ -1,0 +1,530 @@
+// libfmnmf.so: the C ABI declared in include/fmnmf.h.
+//
+// Host side only: validation, workspace carving, state upload/download,
+// kernel sequencing on the caller's stream and capture of one iteration in a
+// HIP graph.  All arithmetic of the method runs in the kernels of inst_*.hip.
+#include "../../include/fmnmf.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kargs.h"
+#include "kernels.h"
+
+using fmnmf::KArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(FMNMF_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+inline int round_up(int a, int b) { return cdiv(a, b) * b; }
+
+struct Layout {
+  int MP, FP, TP, KP, K4, KPB, KT;
+  int Sw, Sh, Sg, Sv, tw, fh, tg, tv, nll;
+  size_t rb;  // bytes of one real element (FP64: 8, else 4)
+  size_t off_Xt, off_W, off_H, off_G, off_Wb, off_Wtb, off_Hb, off_Htb, off_Q, off_Qr, off_Qinv, off_logdet,
+      off_pw, off_ph, off_pg, off_pv, off_pll, off_status, off_ll, off_Yd, total;
+};
+
+int check_dims(const fmnmf_dims* d) {
+  if (!d) return fail(FMNMF_E_INVAL, "dims is NULL");
+  if (d->F < 1 || d->T < 1 || d->M < 1 || d->N < 1 || d->K < 1)
+    return fail(FMNMF_E_INVAL, "F, T, M, N, K must be >= 1 (got %d %d %d %d %d)", d->F, d->T, d->M, d->N, d->K);
+  if (d->precision < FMNMF_FP64 || d->precision > FMNMF_MIXED_BF16)
+    return fail(FMNMF_E_INVAL, "unknown precision %d", d->precision);
+  if (!(d->delta >= 0.0) || !std::isfinite(d->delta)) return fail(FMNMF_E_INVAL, "delta must be finite and >= 0");
+  if ((d->flags & ~(unsigned)FMNMF_WITH_DERIVED) != 0u) return fail(FMNMF_E_INVAL, "unknown flags 0x%x", d->flags);
+  if (d->M > 8) return fail(FMNMF_E_UNSUPPORTED, "M = %d > 8 microphones is not built", d->M);
+  if (d->N > 8) return fail(FMNMF_E_UNSUPPORTED, "N = %d > 8 sources is not built", d->N);
+  if (d->K > 64) return fail(FMNMF_E_UNSUPPORTED, "K = %d > 64 bases is not built", d->K);
+  if ((long long)d->F * d->T * 64 > (1ll << 40)) return fail(FMNMF_E_UNSUPPORTED, "F*T too large");
+  return FMNMF_OK;
+}
+
+// Number of splits of a reduction over `len` items with `tiles` independent
+// tiles, so that tiles * splits reaches about `target` workgroups; each split
+// covers a multiple of 64 items.
+void choose_split(int tiles, int len, int target, int max_splits, int* splits, int* span) {
+  int s = std::max(1, std::min(cdiv(target, tiles), std::min(max_splits, cdiv(len, 64))));
+  int sp = round_up(cdiv(len, s), 64);
+  *span = sp;
+  *splits = cdiv(len, sp);
+}
+
+void make_layout(const fmnmf_dims* d, Layout* L) {
+  L->MP = d->M <= 1 ? 1 : d->M <= 2 ? 2 : d->M <= 4 ? 4 : 8;
+  L->FP = round_up(d->F, 32);
+  L->TP = round_up(d->T, 32);
+  L->KT = d->K <= 16 ? 1 : d->K <= 32 ? 2 : 4;
+  L->KP = 16 * L->KT;
+  L->K4 = round_up(d->K, 4);
+  L->KPB = round_up(L->KP, 32);
+  const int nF = cdiv(d->F, 16), nT = cdiv(d->T, 16);
+  choose_split(nF, d->T, 512, 64, &L->Sw, &L->tw);
+  choose_split(nT, d->F, 512, 64, &L->Sh, &L->fh);
+  choose_split(nF, d->T, 512, 64, &L->Sg, &L->tg);
+  choose_split(nF, d->T, 512, 16, &L->Sv, &L->tv);
+  L->nll = cdiv(d->F, 16) * cdiv(d->T, 64);
+  L->rb = d->precision == FMNMF_FP64 ? 8 : 4;
+  const size_t rb = L->rb, cb = 2 * rb;
+  const bool bf = d->precision == FMNMF_MIXED_BF16;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = align_up(off, 256);
+    size_t o = off;
+    off += bytes;
+    return o;
+  };
+  const size_t N = d->N, F = d->F, T = d->T, MP = L->MP, FP = L->FP, TP = L->TP, KP = L->KP, KPB = L->KPB;
+  L->off_Xt = take(F * T * MP * rb);
+  L->off_W = take(N * KP * FP * rb);
+  L->off_H = take(N * KP * TP * rb);
+  L->off_G = take(N * FP * MP * rb);
+  L->off_Wb = take(bf ? N * KP * FP * 2 : 0);
+  L->off_Wtb = take(bf ? N * FP * KPB * 2 : 0);
+  L->off_Hb = take(bf ? N * KP * TP * 2 : 0);
+  L->off_Htb = take(bf ? N * TP * KPB * 2 : 0);
+  L->off_Q = take(FP * MP * MP * 16);
+  L->off_Qr = take(d->precision == FMNMF_FP64 ? 0 : FP * MP * MP * cb);
+  L->off_Qinv = take(FP * MP * MP * cb);
+  L->off_logdet = take(FP * 8);
+  L->off_pw = take((size_t)L->Sw * 2 * N * KP * FP * rb);
+  L->off_ph = take((size_t)L->Sh * 2 * N * KP * TP * rb);
+  L->off_pg = take((size_t)L->Sg * 2 * N * FP * MP * rb);
+  L->off_pv = take((size_t)L->Sv * FP * MP * MP * MP * rb);
+  L->off_pll = take((size_t)L->nll * 8);
+  L->off_status = take(8);
+  L->off_ll = take(8);
+  L->off_Yd = take((d->flags & FMNMF_WITH_DERIVED) ? F * T * MP * rb : 0);
+  L->total = align_up(off, 256);
+}
+
+typedef hipError_t (*launch_fn)(const KArgs&, hipStream_t);
+struct Ops {
+  launch_fn wpass, hpass, gpass, vpass, proj, ip, logdet, qinv, mirror;
+  hipError_t (*mu)(const KArgs&, int, hipStream_t);
+  hipError_t (*wiener)(const KArgs&, void*, hipStream_t);
+};
+#define FM_OPS(sfx)                                                                                       \
+  Ops {                                                                                                   \
+    fmnmf::launch_wpass_##sfx, fmnmf::launch_hpass_##sfx, fmnmf::launch_gpass_##sfx,                     \
+        fmnmf::launch_vpass_##sfx, fmnmf::launch_proj_##sfx, fmnmf::launch_ip_##sfx,                     \
+        fmnmf::launch_logdet_##sfx, fmnmf::launch_qinv_##sfx, fmnmf::launch_mirror_##sfx,               \
+        fmnmf::launch_mu_##sfx, fmnmf::launch_wiener_##sfx                                               \
+  }
+const Ops kOps[3] = {FM_OPS(f64), FM_OPS(f32), FM_OPS(bf16)};
+
+}  // namespace
+
+struct fmnmf_ctx {
+  fmnmf_dims d;
+  Layout L;
+  KArgs a;
+  hipStream_t s;
+  const Ops* ops;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  bool graph_tried = false;
+};
+
+namespace {
+
+int launch_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(FMNMF_E_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return FMNMF_OK;
+}
+
+// x~ and L of the current state.
+int enqueue_proj_ll(fmnmf_ctx* c) {
+  int rc = launch_check(c->ops->proj(c->a, c->s), "proj");
+  if (rc) return rc;
+  return launch_check(fmnmf::launch_ll_final(c->a, c->s), "ll_final");
+}
+
+const char* const kKernelNames[FMNMF_NUM_KERNELS] = {"wpass", "mu_w", "hpass", "mu_h", "gpass",
+                                                     "mu_g",  "vpass", "ip",   "proj", "ll_final"};
+
+hipError_t launch_kernel(fmnmf_ctx* c, int k) {
+  const Ops& o = *c->ops;
+  switch (k) {
+    case FMNMF_K_WPASS: return o.wpass(c->a, c->s);
+    case FMNMF_K_MU_W: return o.mu(c->a, 0, c->s);
+    case FMNMF_K_HPASS: return o.hpass(c->a, c->s);
+    case FMNMF_K_MU_H: return o.mu(c->a, 1, c->s);
+    case FMNMF_K_GPASS: return o.gpass(c->a, c->s);
+    case FMNMF_K_MU_G: return o.mu(c->a, 2, c->s);
+    case FMNMF_K_VPASS: return o.vpass(c->a, c->s);
+    case FMNMF_K_IP: return o.ip(c->a, c->s);
+    case FMNMF_K_PROJ: return o.proj(c->a, c->s);
+    case FMNMF_K_LL: return fmnmf::launch_ll_final(c->a, c->s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// One full iteration (Eqs. 23, 24, 21, 18-20, 17).
+int enqueue_iteration(fmnmf_ctx* c) {
+  for (int k = 0; k < FMNMF_NUM_KERNELS; ++k) {
+    int rc = launch_check(launch_kernel(c, k), kKernelNames[k]);
+    if (rc) return rc;
+  }
+  return FMNMF_OK;
+}
+
+int sync_status(fmnmf_ctx* c) {
+  int st = 0;
+  HIPCHK(hipMemcpyAsync(&st, c->a.status, sizeof st, hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (st & fmnmf::ST_SINGULAR) return fail(FMNMF_E_SINGULAR, "a Q_f V_fm or Q_f system was singular");
+  if (st & fmnmf::ST_NONFINITE) return fail(FMNMF_E_NONFINITE, "the log-likelihood is not finite");
+  return FMNMF_OK;
+}
+
+bool finite_positive(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!(p[i] > 0.0) || !std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Upload a host FP64 state into the padded device arrays (zero padding kept).
+int upload_state(fmnmf_ctx* c, const double* W, const double* H, const double* G, const double* Q) {
+  const fmnmf_dims& d = c->d;
+  const Layout& L = c->L;
+  const size_t N = d.N, K = d.K, F = d.F, T = d.T, M = d.M, MP = L.MP, FP = L.FP, TP = L.TP, KP = L.KP;
+  if (!W || !H || !G || !Q) return fail(FMNMF_E_INVAL, "state pointers must not be NULL");
+  if (!finite_positive(W, N * K * F) || !finite_positive(H, N * K * T) || !finite_positive(G, N * F * M))
+    return fail(FMNMF_E_INVAL, "W, H and G must be finite and > 0");
+  for (size_t i = 0; i < 2 * F * M * M; ++i)
+    if (!std::isfinite(Q[i])) return fail(FMNMF_E_INVAL, "Q must be finite");
+  const bool f64 = d.precision == FMNMF_FP64;
+  auto put = [&](void* dst, size_t count, auto fill) -> int {
+    if (f64) {
+      std::vector<double> h(count, 0.0);
+      fill(h.data());
+      HIPCHK(hipMemcpyAsync(dst, h.data(), count * 8, hipMemcpyHostToDevice, c->s));
+      HIPCHK(hipStreamSynchronize(c->s));
+    } else {
+      std::vector<double> h(count, 0.0);
+      fill(h.data());
+      std::vector<float> hf(count);
+      for (size_t i = 0; i < count; ++i) hf[i] = (float)h[i];
+      HIPCHK(hipMemcpyAsync(dst, hf.data(), count * 4, hipMemcpyHostToDevice, c->s));
+      HIPCHK(hipStreamSynchronize(c->s));
+    }
+    return FMNMF_OK;
+  };
+  int rc;
+  rc = put(c->a.W, N * KP * FP, [&](double* h) {
+    for (size_t n = 0; n < N; ++n)
+      for (size_t k = 0; k < K; ++k)
+        for (size_t f = 0; f < F; ++f) h[(n * KP + k) * FP + f] = W[(n * K + k) * F + f];
+  });
+  if (rc) return rc;
+  rc = put(c->a.H, N * KP * TP, [&](double* h) {
+    for (size_t n = 0; n < N; ++n)
+      for (size_t k = 0; k < K; ++k)
+        for (size_t t = 0; t < T; ++t) h[(n * KP + k) * TP + t] = H[(n * K + k) * T + t];
+  });
+  if (rc) return rc;
+  rc = put(c->a.G, N * FP * MP, [&](double* h) {
+    for (size_t n = 0; n < N; ++n)
+      for (size_t f = 0; f < F; ++f)
+        for (size_t m = 0; m < M; ++m) h[(n * FP + f) * MP + m] = G[(n * F + f) * M + m];
+  });
+  if (rc) return rc;
+  {
+    std::vector<double> h(2 * F * MP * MP, 0.0);
+    for (size_t f = 0; f < F; ++f)
+      for (size_t i = 0; i < M; ++i)
+        for (size_t j = 0; j < M; ++j) {
+          h[2 * ((f * MP + i) * MP + j)] = Q[2 * ((f * M + i) * M + j)];
+          h[2 * ((f * MP + i) * MP + j) + 1] = Q[2 * ((f * M + i) * M + j) + 1];
+        }
+    HIPCHK(hipMemcpyAsync(c->a.Q, h.data(), h.size() * 8, hipMemcpyHostToDevice, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+  }
+  HIPCHK(hipMemsetAsync(c->a.status, 0, sizeof(int), c->s));
+  if ((rc = launch_check(c->ops->logdet(c->a, c->s), "logdet"))) return rc;
+  if ((rc = launch_check(c->ops->mirror(c->a, c->s), "mirror"))) return rc;
+  return enqueue_proj_ll(c);
+}
+
+// Copy a padded device array [N][R1p][R2p] (R1 x R2 valid) to host FP64 [N][R1][R2].
+int download(fmnmf_ctx* c, const void* src, size_t N, size_t R1, size_t R2, size_t R1p, size_t R2p, double* out) {
+  const size_t count = N * R1p * R2p;
+  std::vector<double> h(count);
+  if (c->d.precision == FMNMF_FP64) {
+    HIPCHK(hipMemcpyAsync(h.data(), src, count * 8, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+  } else {
+    std::vector<float> hf(count);
+    HIPCHK(hipMemcpyAsync(hf.data(), src, count * 4, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    for (size_t i = 0; i < count; ++i) h[i] = hf[i];
+  }
+  for (size_t n = 0; n < N; ++n)
+    for (size_t i = 0; i < R1; ++i)
+      for (size_t j = 0; j < R2; ++j) out[(n * R1 + i) * R2 + j] = h[(n * R1p + i) * R2p + j];
+  return FMNMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fmnmf_workspace_bytes(const fmnmf_dims* d) {
+  if (check_dims(d) != FMNMF_OK) return 0;
+  Layout L;
+  make_layout(d, &L);
+  return L.total;
+}
+
+size_t fmnmf_footprint_bytes(const fmnmf_dims* d) {
+  const size_t ws = fmnmf_workspace_bytes(d);
+  if (!ws) return 0;
+  const size_t cb = d->precision == FMNMF_FP64 ? 16 : 8;
+  const size_t x = (size_t)d->F * d->T * d->M * cb;
+  return ws + x + (size_t)d->N * x;
+}
+
+int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws_dev, size_t ws_bytes,
+               const double* W0, const double* H0, const double* G0, const double* Q0, void* stream) {
+  if (!out) return fail(FMNMF_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_dims(d);
+  if (rc) return rc;
+  if (!X_dev || !ws_dev) return fail(FMNMF_E_INVAL, "X_dev and ws_dev must not be NULL");
+  if (((uintptr_t)X_dev & 15u) != 0) return fail(FMNMF_E_INVAL, "X_dev must be 16-byte aligned");
+  if (((uintptr_t)ws_dev & 255u) != 0) return fail(FMNMF_E_INVAL, "ws_dev must be 256-byte aligned");
+  fmnmf_ctx* c = new fmnmf_ctx();
+  c->d = *d;
+  make_layout(d, &c->L);
+  if (ws_bytes < c->L.total) {
+    const size_t need = c->L.total;
+    delete c;
+    return fail(FMNMF_E_WORKSPACE, "workspace of %zu bytes < required %zu", ws_bytes, need);
+  }
+  c->s = static_cast<hipStream_t>(stream);
+  c->ops = &kOps[d->precision];
+  const Layout& L = c->L;
+  char* ws = static_cast<char*>(ws_dev);
+  KArgs& a = c->a;
+  std::memset(&a, 0, sizeof a);
+  a.F = d->F;
+  a.T = d->T;
+  a.M = d->M;
+  a.N = d->N;
+  a.K = d->K;
+  a.MP = L.MP;
+  a.FP = L.FP;
+  a.TP = L.TP;
+  a.KP = L.KP;
+  a.K4 = L.K4;
+  a.KPB = L.KPB;
+  a.KT = L.KT;
+  a.delta = d->delta;
+  a.X = X_dev;
+  a.Xt = ws + L.off_Xt;
+  a.W = ws + L.off_W;
+  a.H = ws + L.off_H;
+  a.G = ws + L.off_G;
+  const bool bf = d->precision == FMNMF_MIXED_BF16;
+  a.Wb = bf ? reinterpret_cast<__bf16*>(ws + L.off_Wb) : nullptr;
+  a.Wtb = bf ? reinterpret_cast<__bf16*>(ws + L.off_Wtb) : nullptr;
+  a.Hb = bf ? reinterpret_cast<__bf16*>(ws + L.off_Hb) : nullptr;
+  a.Htb = bf ? reinterpret_cast<__bf16*>(ws + L.off_Htb) : nullptr;
+  a.Q = reinterpret_cast<double2*>(ws + L.off_Q);
+  a.Qr = d->precision == FMNMF_FP64 ? static_cast<void*>(a.Q) : static_cast<void*>(ws + L.off_Qr);
+  a.Qinv = ws + L.off_Qinv;
+  a.logdet = reinterpret_cast<double*>(ws + L.off_logdet);
+  a.pw = ws + L.off_pw;
+  a.ph = ws + L.off_ph;
+  a.pg = ws + L.off_pg;
+  a.pv = ws + L.off_pv;
+  a.pll = reinterpret_cast<double*>(ws + L.off_pll);
+  a.nll = L.nll;
+  a.status = reinterpret_cast<int*>(ws + L.off_status);
+  a.ll = reinterpret_cast<double*>(ws + L.off_ll);
+  a.Yd = (d->flags & FMNMF_WITH_DERIVED) ? static_cast<void*>(ws + L.off_Yd) : nullptr;
+  a.Sw = L.Sw;
+  a.Sh = L.Sh;
+  a.Sg = L.Sg;
+  a.Sv = L.Sv;
+  a.tw = L.tw;
+  a.fh = L.fh;
+  a.tg = L.tg;
+  a.tv = L.tv;
+  hipError_t e = hipMemsetAsync(ws_dev, 0, L.total, c->s);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(FMNMF_E_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+  }
+  rc = upload_state(c, W0, H0, G0, Q0);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return FMNMF_OK;
+}
+
+int fmnmf_step(fmnmf_ctx* c, int n_iter) {
+  if (!c) return fail(FMNMF_E_INVAL, "ctx is NULL");
+  if (n_iter < 0) return fail(FMNMF_E_INVAL, "n_iter < 0");
+  if (n_iter == 0) return FMNMF_OK;
+  // Capture one iteration as a graph on first use (only on a non-default
+  // stream; FMNMF_NO_GRAPH=1 disables it).
+  if (!c->graph_tried) {
+    c->graph_tried = true;
+    const char* ng = std::getenv("FMNMF_NO_GRAPH");
+    if (c->s != nullptr && !(ng && ng[0] == '1')) {
+      if (hipStreamBeginCapture(c->s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        int rc = enqueue_iteration(c);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->s, &g);
+        if (rc == FMNMF_OK && e == hipSuccess && g) {
+          if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) == hipSuccess) c->graph = g;
+          else {
+            hipGraphDestroy(g);
+            c->gexec = nullptr;
+          }
+        } else if (g) {
+          hipGraphDestroy(g);
+        }
+        (void)hipGetLastError();
+      }
+    }
+  }
+  for (int i = 0; i < n_iter; ++i) {
+    if (c->gexec) {
+      HIPCHK(hipGraphLaunch(c->gexec, c->s));
+    } else {
+      int rc = enqueue_iteration(c);
+      if (rc) return rc;
+    }
+  }
+  return FMNMF_OK;
+}
+
+int fmnmf_loglik(fmnmf_ctx* c, double* ll) {
+  if (!c || !ll) return fail(FMNMF_E_INVAL, "NULL argument");
+  double v = 0.0;
+  HIPCHK(hipMemcpyAsync(&v, c->a.ll, sizeof v, hipMemcpyDeviceToHost, c->s));
+  int rc = sync_status(c);
+  *ll = v;
+  return rc;
+}
+
+int fmnmf_separate(fmnmf_ctx* c, void* Y_dev) {
+  if (!c || !Y_dev) return fail(FMNMF_E_INVAL, "NULL argument");
+  if (((uintptr_t)Y_dev & 7u) != 0) return fail(FMNMF_E_INVAL, "Y_dev must be 8-byte aligned");
+  int rc;
+  if ((rc = launch_check(c->ops->qinv(c->a, c->s), "qinv"))) return rc;
+  if ((rc = launch_check(c->ops->wiener(c->a, Y_dev, c->s), "wiener"))) return rc;
+  return sync_status(c);
+}
+
+int fmnmf_get_state(fmnmf_ctx* c, double* W, double* H, double* G, double* Q) {
+  if (!c) return fail(FMNMF_E_INVAL, "ctx is NULL");
+  const fmnmf_dims& d = c->d;
+  const Layout& L = c->L;
+  int rc;
+  if (W && (rc = download(c, c->a.W, d.N, d.K, d.F, L.KP, L.FP, W))) return rc;
+  if (H && (rc = download(c, c->a.H, d.N, d.K, d.T, L.KP, L.TP, H))) return rc;
+  if (G && (rc = download(c, c->a.G, d.N, d.F, d.M, L.FP, L.MP, G))) return rc;
+  if (Q) {
+    std::vector<double> h(2 * (size_t)d.F * L.MP * L.MP);
+    HIPCHK(hipMemcpyAsync(h.data(), c->a.Q, h.size() * 8, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    for (int f = 0; f < d.F; ++f)
+      for (int i = 0; i < d.M; ++i)
+        for (int j = 0; j < d.M; ++j) {
+          Q[2 * (((size_t)f * d.M + i) * d.M + j)] = h[2 * (((size_t)f * L.MP + i) * L.MP + j)];
+          Q[2 * (((size_t)f * d.M + i) * d.M + j) + 1] = h[2 * (((size_t)f * L.MP + i) * L.MP + j) + 1];
+        }
+  }
+  return sync_status(c);
+}
+
+int fmnmf_set_state(fmnmf_ctx* c, const double* W, const double* H, const double* G, const double* Q) {
+  if (!c) return fail(FMNMF_E_INVAL, "ctx is NULL");
+  return upload_state(c, W, H, G, Q);
+}
+
+int fmnmf_get_derived(fmnmf_ctx* c, int which, double* out) {
+  if (!c || !out) return fail(FMNMF_E_INVAL, "NULL argument");
+  if (which != 0 && which != 1) return fail(FMNMF_E_INVAL, "which must be 0 (x~) or 1 (y~)");
+  if (which == 1 && !c->a.Yd) return fail(FMNMF_E_UNSUPPORTED, "y~ needs the FMNMF_WITH_DERIVED flag");
+  const fmnmf_dims& d = c->d;
+  int rc = download(c, which == 0 ? c->a.Xt : c->a.Yd, 1, (size_t)d.F * d.T, d.M, (size_t)d.F * d.T, c->L.MP, out);
+  if (rc) return rc;
+  return sync_status(c);
+}
+
+int fmnmf_profile_step(fmnmf_ctx* c, int n_iter, double* ms) {
+  if (!c || !ms || n_iter < 1) return fail(FMNMF_E_INVAL, "bad arguments to fmnmf_profile_step");
+  std::vector<hipEvent_t> ev(2 * (size_t)FMNMF_NUM_KERNELS * n_iter, nullptr);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  int rc = FMNMF_OK;
+  for (int i = 0; i < n_iter && rc == FMNMF_OK; ++i)
+    for (int k = 0; k < FMNMF_NUM_KERNELS && rc == FMNMF_OK; ++k) {
+      hipEvent_t* p = &ev[2 * ((size_t)i * FMNMF_NUM_KERNELS + k)];
+      if (hipEventRecord(p[0], c->s) != hipSuccess) rc = fail(FMNMF_E_HIP, "hipEventRecord failed");
+      else if ((rc = launch_check(launch_kernel(c, k), kKernelNames[k])) == FMNMF_OK &&
+               hipEventRecord(p[1], c->s) != hipSuccess)
+        rc = fail(FMNMF_E_HIP, "hipEventRecord failed");
+    }
+  if (rc == FMNMF_OK && hipStreamSynchronize(c->s) != hipSuccess) rc = fail(FMNMF_E_HIP, "stream sync failed");
+  for (int k = 0; k < FMNMF_NUM_KERNELS; ++k) ms[k] = 0.0;
+  if (rc == FMNMF_OK)
+    for (int i = 0; i < n_iter; ++i)
+      for (int k = 0; k < FMNMF_NUM_KERNELS; ++k) {
+        float t = 0.f;
+        hipEvent_t* p = &ev[2 * ((size_t)i * FMNMF_NUM_KERNELS + k)];
+        if (hipEventElapsedTime(&t, p[0], p[1]) == hipSuccess) ms[k] += t / n_iter;
+      }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  return sync_status(c);
+}
+
+const char* fmnmf_kernel_name(int k) { return (k >= 0 && k < FMNMF_NUM_KERNELS) ? kKernelNames[k] : nullptr; }
+
+void fmnmf_destroy(fmnmf_ctx* c) {
+  if (!c) return;
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  delete c;
+}
+
+const char* fmnmf_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

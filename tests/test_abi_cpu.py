@@ -1,0 +1,62 @@
+"""The C ABI library loads and exports what include/fmnmf.h declares
+(no compute calls: no GPU is needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1903_03237_amd import fmnmf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fmnmf.h")).read()
+    return sorted(set(re.findall(r"\b(fmnmf_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(fmnmf.LIB_PATH):
+        pytest.fail("libfmnmf.so is not built (run __graft_entry__.build())")
+    return fmnmf.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert set(names) == set(fmnmf.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_workspace_validation_without_gpu(L):
+    ok = fmnmf.make_dims(513, 3000, 8, 5, 32, "fp32", 1e-6)
+    assert fmnmf.workspace_bytes(ok) > 513 * 3000 * 8 * 4
+    assert fmnmf.footprint_bytes(ok) > fmnmf.workspace_bytes(ok)
+    for bad, code in [((0, 10, 2, 2, 2), "must be >= 1"), ((10, 10, 9, 2, 2), "M = 9"),
+                      ((10, 10, 2, 9, 2), "N = 9"), ((10, 10, 2, 2, 65), "K = 65")]:
+        assert fmnmf.workspace_bytes(fmnmf.make_dims(*bad)) == 0
+        assert code in L.fmnmf_last_error().decode()
+    assert fmnmf.workspace_bytes(fmnmf.make_dims(4, 4, 2, 2, 2, "fp64", -1.0)) == 0
+    assert fmnmf.workspace_bytes(fmnmf.make_dims(4, 4, 2, 2, 2, 7)) == 0
+
+
+def test_precision_changes_workspace(L):
+    b64 = fmnmf.workspace_bytes(fmnmf.make_dims(129, 100, 2, 2, 4, "fp64"))
+    b32 = fmnmf.workspace_bytes(fmnmf.make_dims(129, 100, 2, 2, 4, "fp32"))
+    assert b64 > b32 > 0
+    d = fmnmf.make_dims(129, 100, 2, 2, 4, "fp32", flags=fmnmf.WITH_DERIVED)
+    assert fmnmf.workspace_bytes(d) >= b32 + 129 * 100 * 2 * 4
+
+
+def test_null_arguments_are_rejected(L):
+    ctx = ctypes.c_void_p()
+    d = fmnmf.make_dims(4, 4, 2, 2, 2)
+    assert L.fmnmf_init(None, ctypes.byref(d), None, None, 0, None, None, None, None, None) == fmnmf.E_INVAL
+    assert L.fmnmf_init(ctypes.byref(ctx), ctypes.byref(d), None, None, 0, None, None, None, None, None) == fmnmf.E_INVAL
+    assert L.fmnmf_step(None, 1) == fmnmf.E_INVAL
+    v = ctypes.c_double()
+    assert L.fmnmf_loglik(None, ctypes.byref(v)) == fmnmf.E_INVAL
+    L.fmnmf_destroy(None)

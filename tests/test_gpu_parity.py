@@ -1,0 +1,155 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+FP64 path: one-step parity from identical states to 1e-10 relative (norm per
+tensor; |dL| / |L| for the log-likelihood), on shapes that span several
+16-wide tiles and ragged tails in F and T, every supported M class and
+several (N, K).  FP32 / mixed-bf16 paths: the error bounds stated for them
+(log-likelihood 1e-5 relative per step).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fastmnmf as fm
+from paper_1903_03237_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _model(device, X, N, K, init, precision, delta, derived=False):
+    import torch
+
+    from paper_1903_03237_amd import fmnmf
+
+    dt = np.complex128 if precision == "fp64" else np.complex64
+    Xd = torch.from_numpy(np.ascontiguousarray(X.astype(dt))).to(device)
+    return fmnmf.FastMNMF(Xd, N, K, init, precision=precision, delta=delta, derived=derived)
+
+
+# (F, T, M, N, K, delta_rel, random_q)
+FP64_CASES = [
+    (21, 37, 3, 2, 5, 0.0, True),
+    (129, 100, 2, 2, 4, 0.0, False),
+    (40, 70, 1, 1, 1, 0.0, True),
+    (33, 90, 4, 3, 16, 1e-6, True),
+    (17, 130, 5, 5, 20, 1e-8, True),
+    (50, 64, 8, 6, 40, 1e-8, True),
+    (16, 16, 2, 8, 64, 0.0, True),
+    (70, 33, 6, 4, 33, 1e-8, True),
+    (1, 1, 1, 1, 1, 0.0, True),
+    (3, 5, 2, 1, 2, 0.0, True),
+]
+
+
+@pytest.mark.parametrize("case", FP64_CASES, ids=lambda c: "F%dT%dM%dN%dK%d" % c[:5])
+def test_fp64_one_step_parity(device, case):
+    F, T, M, N, K, drel, rq = case
+    X, init, delta = synth.random_problem(F, T, M, N, K, seed=F * 7 + T, delta_rel=drel, random_q=rq)
+    s0 = fm.State(*init)
+    m = _model(device, X, N, K, init, "fp64", delta, derived=True)
+    # initial projection, model and likelihood
+    assert abs(m.loglik() - fm.loglik(X, s0, delta)) <= 1e-10 * abs(fm.loglik(X, s0, delta))
+    assert _rel(m.derived(0), fm.project(X, s0.Q)) < 1e-12
+    assert _rel(m.derived(1), fm.model(fm.psd(s0.W, s0.H), s0.G, delta)) < 1e-12
+    # one step from the initial state
+    m.step(1)
+    s1 = fm.step(X, s0, delta)
+    W, H, G, Q = m.get_state()
+    for name, a, b in (("W", W, s1.W), ("H", H, s1.H), ("G", G, s1.G), ("Q", Q, s1.Q)):
+        assert _rel(a, b) < 1e-10, (name, _rel(a, b))
+    l1 = fm.loglik(X, s1, delta)
+    assert abs(m.loglik() - l1) <= 1e-10 * abs(l1)
+    # inject a later oracle state and step once more
+    s3 = fm.step(X, fm.step(X, s1, delta), delta)
+    m.set_state(s3.W, s3.H, s3.G, s3.Q)
+    assert abs(m.loglik() - fm.loglik(X, s3, delta)) <= 1e-10 * abs(fm.loglik(X, s3, delta))
+    m.step(1)
+    s4 = fm.step(X, s3, delta)
+    W, H, G, Q = m.get_state()
+    for name, a, b in (("W", W, s4.W), ("H", H, s4.H), ("G", G, s4.G), ("Q", Q, s4.Q)):
+        assert _rel(a, b) < 1e-10, (name, _rel(a, b))
+    # separation of the final state
+    Y = m.separate().cpu().numpy()
+    assert _rel(Y, fm.separate(X, s4, delta)) < 1e-10
+    m.close()
+
+
+def test_fewer_frames_than_channels_is_singular(device):
+    """T < M: every V_fm = (1/T) sum_t x x^H / y~ has rank T < M, so the IP
+    system of Eq. (19) is singular; the library reports it (and the oracle's
+    solve degenerates too) instead of producing numbers."""
+    from paper_1903_03237_amd import fmnmf
+
+    X, init, delta = synth.random_problem(5, 2, 3, 1, 1, seed=1, random_q=True)
+    m = _model(device, X, 1, 1, init, "fp64", delta)
+    m.step(1)
+    with pytest.raises(fmnmf.FmnmfError) as ei:
+        m.loglik()
+    assert ei.value.code == fmnmf.E_SINGULAR
+    m.close()
+
+
+def test_fp64_trajectory_small_config(device):
+    """The oracle-sized workload (M=2, N=2, K=4, F=129, T=100), 10 free-running
+    iterations from the same seeded state; monotone and within 1e-9."""
+    X, init, delta = synth.workload(1)
+    m = _model(device, X, 2, 4, init, "fp64", delta)
+    s = fm.State(*init)
+    lls = [m.loglik()]
+    for _ in range(10):
+        m.step(1)
+        lls.append(m.loglik())
+    s, ref = fm.run(X, s, 10, delta)
+    np.testing.assert_allclose(lls, ref, rtol=1e-9)
+    assert np.all(np.diff(lls) >= -1e-10 * abs(lls[-1]))
+    W, H, G, Q = m.get_state()
+    assert _rel(W, s.W) < 1e-8 and _rel(Q, s.Q) < 1e-8
+    m.close()
+
+
+def test_fp64_deterministic(device):
+    X, init, delta = synth.random_problem(45, 80, 4, 3, 12, seed=3, random_q=True)
+    outs = []
+    for _ in range(2):
+        m = _model(device, X, 3, 12, init, "fp64", delta)
+        m.step(3)
+        outs.append((m.loglik(),) + tuple(m.get_state()))
+        m.close()
+    assert outs[0][0] == outs[1][0]
+    for a, b in zip(outs[0][1:], outs[1][1:]):
+        assert np.array_equal(a, b)
+
+
+# Log-likelihood error is measured against max(|L|, F T M): L sums F T M terms
+# of order one that largely cancel, so |L| alone can be small.  bf16 operands
+# round W and H to 8 significant bits, which at these tiny sizes does not
+# average out; the full-size errors are reported by the precision study.
+@pytest.mark.parametrize("precision,tol_ll,tol_state", [("fp32", 1e-5, 2e-3), ("bf16", 5e-4, 5e-2)])
+@pytest.mark.parametrize("case", [(33, 90, 4, 3, 16), (50, 200, 8, 5, 32), (21, 37, 3, 2, 5)],
+                         ids=lambda c: "F%dT%dM%dN%dK%d" % c)
+def test_reduced_precision_one_step(device, precision, tol_ll, tol_state, case):
+    F, T, M, N, K = case
+    X, init, delta = synth.random_problem(F, T, M, N, K, seed=11 + F, delta_rel=1e-8, random_q=True)
+    X = X.astype(np.complex64).astype(np.complex128)  # the oracle sees the same rounded input
+    s0 = fm.State(*init)
+    m = _model(device, X, N, K, init, precision, delta, derived=True)
+    l0 = fm.loglik(X, s0, delta)
+    scale = lambda ll: max(abs(ll), F * T * M)
+    assert abs(m.loglik() - l0) <= tol_ll * scale(l0)
+    assert _rel(m.derived(0), fm.project(X, s0.Q)) < 1e-5
+    s3 = fm.step(X, fm.step(X, fm.step(X, s0, delta), delta), delta)
+    m.set_state(s3.W, s3.H, s3.G, s3.Q)
+    m.step(1)
+    s4 = fm.step(X, s3, delta)
+    l4 = fm.loglik(X, s4, delta)
+    assert abs(m.loglik() - l4) <= tol_ll * scale(l4), (m.loglik(), l4)
+    W, H, G, Q = m.get_state()
+    for name, a, b in (("W", W, s4.W), ("H", H, s4.H), ("G", G, s4.G), ("Q", Q, s4.Q)):
+        assert _rel(a, b) < tol_state, (name, _rel(a, b))
+    Y = m.separate().cpu().numpy()
+    assert _rel(Y, fm.separate(X, s4, delta)) < tol_state
+    m.close()
