@@ -104,7 +104,9 @@ int fmnmf_step(fmnmf_ctx* c, int n_iter);
 
 /* Synchronise the context's stream and return the log-likelihood of Eq. (17)
  * (without the constant -F T M log(pi)) after the last completed iteration
- * (L_0 right after fmnmf_init or fmnmf_set_state). */
+ * (L_0 right after fmnmf_init or fmnmf_set_state).  Every iteration leaves
+ * per-block partial sums of Eq. (17) on the device; this call adds them in a
+ * fixed order. */
 int fmnmf_loglik(fmnmf_ctx* c, double* ll);
 
 /* Multichannel Wiener filter of the current parameters into Y_dev
@@ -127,16 +129,15 @@ int fmnmf_get_derived(fmnmf_ctx* c, int which, double* out);
 
 /* Kernels of one iteration, in launch order, for fmnmf_profile_step. */
 enum fmnmf_kernel {
-  FMNMF_K_WPASS = 0, /* W numerators/denominators (Eq. 23 sums), split partials */
-  FMNMF_K_MU_W,      /* W multiplicative update                                */
-  FMNMF_K_HPASS,     /* H numerators/denominators (Eq. 24 sums)                */
-  FMNMF_K_MU_H,      /* H multiplicative update                                */
-  FMNMF_K_GPASS,     /* G~ numerators/denominators (Eq. 21 sums)               */
-  FMNMF_K_MU_G,      /* G~ multiplicative update                               */
-  FMNMF_K_VPASS,     /* V_fm accumulation (Eq. 18)                             */
-  FMNMF_K_IP,        /* IP solve + normalisation + log-det (Eqs. 19-20)        */
-  FMNMF_K_PROJ,      /* x~ = |Q x|^2 and the likelihood terms (Eq. 17)         */
-  FMNMF_K_LL,        /* final likelihood reduction                             */
+  FMNMF_K_WPASS = 0, /* W numerators/denominators (Eq. 23), split partials       */
+  FMNMF_K_MU_W,      /* W multiplicative update                                 */
+  FMNMF_K_HPASS,     /* H numerators/denominators (Eq. 24)                      */
+  FMNMF_K_MU_H,      /* H multiplicative update                                 */
+  FMNMF_K_GPASS,     /* G~ numerators/denominators (Eq. 21)                     */
+  FMNMF_K_MU_G,      /* G~ multiplicative update                                */
+  FMNMF_K_VPASS,     /* V_fm accumulation (Eq. 18), split partials              */
+  FMNMF_K_IP,        /* V_fm, IP solve + normalisation + log-det (Eqs. 18-20)   */
+  FMNMF_K_PROJ,      /* x~ = |Q x|^2 and per-block likelihood terms (Eq. 17)    */
   FMNMF_NUM_KERNELS
 };
 

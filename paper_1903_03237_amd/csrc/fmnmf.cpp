@@ -80,7 +80,7 @@ void choose_split(int tiles, int len, int target, int max_splits, int* splits, i
 }
 
 void make_layout(const fmnmf_dims* d, Layout* L) {
-  L->MP = d->M <= 1 ? 1 : d->M <= 2 ? 2 : d->M <= 4 ? 4 : 8;
+  L->MP = d->M <= 2 ? 2 : d->M <= 4 ? 4 : 8;
   L->FP = round_up(d->F, 32);
   L->TP = round_up(d->T, 32);
   L->KT = d->K <= 16 ? 1 : d->K <= 32 ? 2 : 4;
@@ -88,10 +88,13 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   L->K4 = round_up(d->K, 4);
   L->KPB = round_up(L->KP, 32);
   const int nF = cdiv(d->F, 16), nT = cdiv(d->T, 16);
-  choose_split(nF, d->T, 512, 64, &L->Sw, &L->tw);
-  choose_split(nT, d->F, 512, 64, &L->Sh, &L->fh);
-  choose_split(nF, d->T, 512, 64, &L->Sg, &L->tg);
-  choose_split(nF, d->T, 512, 16, &L->Sv, &L->tv);
+  // target number of workgroups of each pass (FMNMF_WG_TARGET overrides)
+  int target = 512;
+  if (const char* e = std::getenv("FMNMF_WG_TARGET")) target = std::max(1, std::atoi(e));
+  choose_split(nF, d->T, target, 64, &L->Sw, &L->tw);
+  choose_split(nT, d->F, target, 64, &L->Sh, &L->fh);
+  choose_split(nF, d->T, target, 64, &L->Sg, &L->tg);
+  choose_split(nF, d->T, target, 16, &L->Sv, &L->tv);
   L->nll = cdiv(d->F, 16) * cdiv(d->T, 64);
   L->rb = d->precision == FMNMF_FP64 ? 8 : 4;
   const size_t rb = L->rb, cb = 2 * rb;
@@ -162,15 +165,11 @@ int launch_check(hipError_t e, const char* what) {
   return FMNMF_OK;
 }
 
-// x~ and L of the current state.
-int enqueue_proj_ll(fmnmf_ctx* c) {
-  int rc = launch_check(c->ops->proj(c->a, c->s), "proj");
-  if (rc) return rc;
-  return launch_check(fmnmf::launch_ll_final(c->a, c->s), "ll_final");
-}
+// x~ and the likelihood partials of the current state.
+int enqueue_proj_ll(fmnmf_ctx* c) { return launch_check(c->ops->proj(c->a, c->s), "proj"); }
 
 const char* const kKernelNames[FMNMF_NUM_KERNELS] = {"wpass", "mu_w", "hpass", "mu_h", "gpass",
-                                                     "mu_g",  "vpass", "ip",   "proj", "ll_final"};
+                                                     "mu_g",  "vpass", "ip",    "proj"};
 
 hipError_t launch_kernel(fmnmf_ctx* c, int k) {
   const Ops& o = *c->ops;
@@ -184,7 +183,6 @@ hipError_t launch_kernel(fmnmf_ctx* c, int k) {
     case FMNMF_K_VPASS: return o.vpass(c->a, c->s);
     case FMNMF_K_IP: return o.ip(c->a, c->s);
     case FMNMF_K_PROJ: return o.proj(c->a, c->s);
-    case FMNMF_K_LL: return fmnmf::launch_ll_final(c->a, c->s);
   }
   return hipErrorInvalidValue;
 }
@@ -435,6 +433,8 @@ int fmnmf_step(fmnmf_ctx* c, int n_iter) {
 
 int fmnmf_loglik(fmnmf_ctx* c, double* ll) {
   if (!c || !ll) return fail(FMNMF_E_INVAL, "NULL argument");
+  int rc0 = launch_check(fmnmf::launch_ll_final(c->a, c->s), "ll_final");
+  if (rc0) return rc0;
   double v = 0.0;
   HIPCHK(hipMemcpyAsync(&v, c->a.ll, sizeof v, hipMemcpyDeviceToHost, c->s));
   int rc = sync_status(c);

@@ -15,6 +15,7 @@ namespace fmnmf {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));  // four bf16 bit patterns
 
 // ---------------------------------------------------------------------------
 // Precision policies.
@@ -23,8 +24,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // and four rows row(l, v), v = 0..3.  Measured layouts on gfx950:
 //   v_mfma_f32_16x16x4_f32 / v_mfma_f32_16x16x32_bf16 : row = 4*(l>>4) + v
 //   v_mfma_f64_16x16x4_f64                           : row = (l>>4) + 4*v
+//   v_mfma_f32_16x16x16_bf16 (K=16)                : row = 4*(l>>4) + v
 // Operands: A[row = l & 15][k], B[k][col = l & 15] with k = (l >> 4) for the
-// K=4 forms and k = 8*(l >> 4) + j (j = 0..7) for the K=32 bf16 form.
+// K=4 forms, k = 4*(l >> 4) + j (j = 0..3) for the K=16 bf16 form and
+// k = 8*(l >> 4) + j (j = 0..7) for the K=32 bf16 form.
 // ---------------------------------------------------------------------------
 
 struct P64 {  // plain FP64 path
@@ -60,14 +63,23 @@ struct PBF {  // FP32 bulk, BF16 operands into MFMA for the NMF contractions
   using R2 = float2;
   using Acc = float;
   using Acc4 = f32x4;
-  static constexpr int KSTEP = 32;
-  static constexpr int TSUB = 2;  // one K=32 MFMA spans two 16-wide sub-tiles
+  static constexpr int KSTEP = 32;  // lambda: K=32 over the bases
+  static constexpr int TSUB = 1;
   static constexpr bool BF = true;
   __device__ static __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
   __device__ static __forceinline__ Acc4 mma(bf16x8 a, bf16x8 b, Acc4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
+  // contractions over 16 bins: K=16, the lane's four bins are its four k
+  __device__ static __forceinline__ Acc4 mma16(i16x4 a, i16x4 b, Acc4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
 };
+
+__device__ __forceinline__ short bf16_bits(float x) {
+  const __bf16 b = (__bf16)x;
+  return __builtin_bit_cast(short, b);
+}
 
 template <class A4>
 __device__ __forceinline__ A4 zero4() {
@@ -106,46 +118,77 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// log and reciprocal in the working precision.  FP32: hardware reciprocal
+// refined by one Newton step (about 1 ulp), log via logf.  FP64: IEEE.
 template <class R>
 __device__ __forceinline__ R rlog(R x) { return log(x); }
 template <>
 __device__ __forceinline__ float rlog<float>(float x) { return logf(x); }
+template <class R>
+__device__ __forceinline__ R rcp(R x) { return R(1) / x; }
+template <>
+__device__ __forceinline__ float rcp<float>(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return r * fmaf(-x, r, 2.0f);
+}
 
 // ---------------------------------------------------------------------------
-// PSD tile engine, Eq. (9).
+// PSD tile engine, Eq. (9): lambda_ftn = sum_k w_nkf h_nkt for a 16 x 16 tile.
 //
 // TF = true : rows are frames, columns frequencies.  Lane l gets
 //             lambda(f = f0 + (l & 15), t = t0 + row(l, v)).
 // TF = false: rows are frequencies, columns frames.  Lane l gets
 //             lambda(f = f0 + row(l, v), t = t0 + (l & 15)).
-// f0, t0 are multiples of 16 inside the padded extents, so every operand load
-// is in bounds; padded W / H rows and columns are zero.
+// Operands (either may live in LDS or global memory):
+//   FP32/FP64: hk(k) points at h_n,k,t0 (stride hs between k), wk likewise
+//              for w_n,k,f0 (stride ws); column c = l & 15 is added here.
+//   bf16:      ht points at h_n,t0,0 of the [t][KPB] copy (row stride hs),
+//              wt at w_n,f0,0 of the [f][KPB] copy (row stride ws).
+// The loop over k is fully unrolled (KP = 16 * KT rows, padded rows are
+// zero) so that all operand loads are issued before the MFMA chain.
 // ---------------------------------------------------------------------------
-
-template <class P, bool TF>
-__device__ __forceinline__ typename P::Acc4 lam_tile(const KArgs& a, int n, int f0, int t0, int l) {
+template <class P, bool TF, int KT, class RH, class RW>
+__device__ __forceinline__ typename P::Acc4 lam_tile(const RH* __restrict__ hk, int hs, const RW* __restrict__ wk,
+                                                     int ws, int l) {
   using Acc4 = typename P::Acc4;
   Acc4 acc = zero4<Acc4>();
   const int c = l & 15, g = l >> 4;
   if constexpr (!P::BF) {
     using R = typename P::R;
-    const R* Hn = static_cast<const R*>(a.H) + (size_t)n * a.KP * a.TP;
-    const R* Wn = static_cast<const R*>(a.W) + (size_t)n * a.KP * a.FP;
-    for (int kb = 0; kb < a.K4; kb += 4) {
-      R h = Hn[(size_t)(kb + g) * a.TP + t0 + c];
-      R w = Wn[(size_t)(kb + g) * a.FP + f0 + c];
-      acc = TF ? P::mma(h, w, acc) : P::mma(w, h, acc);
+    constexpr int NK = 4 * KT;  // 16*KT rows / depth 4
+    R h[NK], w[NK];
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      h[i] = hk[(4 * i + g) * hs + c];
+      w[i] = wk[(4 * i + g) * ws + c];
     }
+#pragma unroll
+    for (int i = 0; i < NK; ++i) acc = TF ? P::mma(h[i], w[i], acc) : P::mma(w[i], h[i], acc);
   } else {
-    const __bf16* Hn = a.Htb + (size_t)n * a.TP * a.KPB;
-    const __bf16* Wn = a.Wtb + (size_t)n * a.FP * a.KPB;
-    for (int kb = 0; kb < a.KPB; kb += 32) {
-      bf16x8 h = *reinterpret_cast<const bf16x8*>(Hn + (size_t)(t0 + c) * a.KPB + kb + 8 * g);
-      bf16x8 w = *reinterpret_cast<const bf16x8*>(Wn + (size_t)(f0 + c) * a.KPB + kb + 8 * g);
-      acc = TF ? P::mma(h, w, acc) : P::mma(w, h, acc);
+    constexpr int NK = (16 * KT + 31) / 32;
+    bf16x8 h[NK], w[NK];
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      h[i] = *reinterpret_cast<const bf16x8*>(hk + c * hs + 32 * i + 8 * g);
+      w[i] = *reinterpret_cast<const bf16x8*>(wk + c * ws + 32 * i + 8 * g);
     }
+#pragma unroll
+    for (int i = 0; i < NK; ++i) acc = TF ? P::mma(h[i], w[i], acc) : P::mma(w[i], h[i], acc);
   }
   return acc;
+}
+
+// Per-lane four values at p[row(l, 0..3)] of a contiguous 16-run: one vector
+// load for the FP32 layout (rows 4g..4g+3), four scalar loads for FP64.
+template <class P>
+__device__ __forceinline__ void load4(const typename P::R* __restrict__ p, int l, typename P::R (&o)[4]) {
+  if constexpr (sizeof(typename P::R) == 4) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(p + 4 * (l >> 4));
+    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = p[P::row(l, r)];
+  }
 }
 
 // Device-side error latch (vector-memory atomic on a global word).

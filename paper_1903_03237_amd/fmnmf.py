@@ -25,7 +25,7 @@ EXPORTS = ("fmnmf_workspace_bytes", "fmnmf_footprint_bytes", "fmnmf_init", "fmnm
            "fmnmf_loglik", "fmnmf_separate", "fmnmf_get_state", "fmnmf_set_state",
            "fmnmf_get_derived", "fmnmf_destroy", "fmnmf_last_error", "fmnmf_profile_step",
            "fmnmf_kernel_name")
-KERNELS = ("wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g", "vpass", "ip", "proj", "ll_final")
+KERNELS = ("wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g", "vpass", "ip", "proj")
 
 
 class Dims(ctypes.Structure):
