@@ -46,9 +46,58 @@ def kernel_model(F, T, M, N, K, rb):
         "wpass": {"bytes": FT * M * rb, "flops": FT * (6 * N * K + 6 * N * M), "bound": "hbm"},
         "hpass": {"bytes": FT * M * rb, "flops": FT * (6 * N * K + 6 * N * M), "bound": "hbm"},
         "gpass": {"bytes": FT * M * rb, "flops": FT * (2 * N * K + 6 * N * M), "bound": "hbm"},
-        "vpass": {"bytes": FT * M * cb, "flops": FT * (M * M * (4 + 2 * M) + 2 * N * K), "bound": "alu"},
+        "vpass": {"bytes": FT * M * cb, "flops": FT * (M * M * (4 + 2 * M) + 2 * N * K), "bound": "hbm"},
         "proj": {"bytes": FT * M * (cb + rb), "flops": FT * (8 * M * M + 2 * N * K + 5 * M), "bound": "hbm"},
     }
+
+
+# Source files that define each kernel and its launch shape.
+KERNEL_SOURCES = {
+    "wpass": "nmf_passes.inc", "hpass": "nmf_passes.inc", "gpass": "nmf_passes.inc",
+    "vpass": "spatial.inc", "proj": "spatial.inc", "wiener": "spatial.inc", "ip": "small.inc",
+}
+COMMON_SOURCES = ["kern_common.h", "kargs.h", "launch.inc", "fmnmf.cpp"]
+
+
+def kernel_sources_digest(kernel):
+    """SHA-256 over the HIP sources that define `kernel` and its launch."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1903_03237_amd", "csrc")
+    for name in [KERNEL_SOURCES[kernel], *COMMON_SOURCES]:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, precision):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, scaled by the copy-kernel calibration; None
+    when there is none for this kernel and path or the kernel's sources have
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_fp32_m8_513x3000.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get("kernels", {}).get(f"{kernel}/{precision}")
+    if not e or e.get("sources_sha256") != kernel_sources_digest(kernel):
+        return None
+    return (e["fetch_kib"] * t["fetch_scale"] + e["write_kib"] * t["write_scale"]) * 1024.0
+
+
+def copy_calibration(torch, mib=512):
+    """One plain device-to-device copy of `mib` MiB (the reference kernel for
+    scaling the HBM byte counters)."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def run_gpu(torch, fmnmf, X, init, delta, N, K, precision, steps, warmup, out_cache):
@@ -126,6 +175,8 @@ def main():
     ap.add_argument("--paths", default="bf16,fp32,fp64", help="precision paths to time; first is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding of this "
@@ -139,6 +190,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        print("[bench] copy calibration: 512 MiB device-to-device", file=sys.stderr, flush=True)
+        copy_calibration(torch)
     cfg = synth.CONFIGS[3]
     F, T, M, N, K = cfg.F, cfg.T, cfg.M, cfg.N, cfg.K
     print(f"[bench] generating workload {cfg.name}", file=sys.stderr, flush=True)
@@ -173,7 +227,7 @@ def main():
         roof = {"kernel": dom, "bound": "alu", "achieved": d["flops"] / sec / 1e12, "peak": peak,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom, head)
     roof["algorithmic_per_launch"] = d["bytes"] if d["bound"] == "hbm" else d["flops"]
     roof["avg_launch_ms"] = kms[dom]
 
