@@ -15,7 +15,7 @@ Notation (Sec. II-A, III-A of the paper):
   Xt  [F, T, M]           x~_ftm = |(Q_f x_ft)_m|^2    (definition under Eq. 17)
   Yt  [F, T, M]           y~_ftm = sum_n lambda_ftn g~_nfm (+ delta)
 
-Readings where the paper is silent (each also listed in the design doc):
+Readings where the paper is silent:
   * one iteration updates W (Eq. 23), then H (Eq. 24), then G~ (Eq. 21),
     then every row of every Q_f by iterative projection (Eqs. 18-20), then
     re-projects X~; the model Y~ is rebuilt from the current parameters
