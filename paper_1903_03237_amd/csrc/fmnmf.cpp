@@ -70,11 +70,11 @@ int check_dims(const fmnmf_dims* d) {
 }
 
 // Number of splits of a reduction over `len` items with `tiles` independent
-// tiles, so that tiles * splits reaches about `target` workgroups; each split
-// covers a multiple of 64 items.
-void choose_split(int tiles, int len, int target, int max_splits, int* splits, int* span) {
-  int s = std::max(1, std::min(cdiv(target, tiles), std::min(max_splits, cdiv(len, 64))));
-  int sp = round_up(cdiv(len, s), 64);
+// tiles, so that tiles * splits stays within `slots` workgroups (at most
+// max_splits, at least 1); each split covers a multiple of `gran` items.
+void choose_split(int tiles, int len, int slots, int max_splits, int gran, int* splits, int* span) {
+  int s = std::max(1, std::min(slots / tiles, std::min(max_splits, cdiv(len, gran))));
+  int sp = round_up(cdiv(len, s), gran);
   *span = sp;
   *splits = cdiv(len, sp);
 }
@@ -88,13 +88,20 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   L->K4 = round_up(d->K, 4);
   L->KPB = round_up(L->KP, 32);
   const int nF = cdiv(d->F, 16), nT = cdiv(d->T, 16);
-  // target number of workgroups of each pass (FMNMF_WG_TARGET overrides)
-  int target = 512;
-  if (const char* e = std::getenv("FMNMF_WG_TARGET")) target = std::max(1, std::atoi(e));
-  choose_split(nF, d->T, target, 64, &L->Sw, &L->tw);
-  choose_split(nT, d->F, target, 64, &L->Sh, &L->fh);
-  choose_split(nF, d->T, target, 64, &L->Sg, &L->tg);
-  choose_split(nF, d->T, target, 16, &L->Sv, &L->tv);
+  // Workgroups aimed at per pass (measured at M=8, N=5, K=32, F=513,
+  // T=3000 on MI355X: the best split counts lie near these totals; the G~
+  // pass stays below 512 because its FP32 form holds only two per CU).
+  // FMNMF_WG_TARGET overrides the W / H / G~ targets.
+  int tw = 660, th = 752, tg = 480;
+  if (const char* e = std::getenv("FMNMF_WG_TARGET")) tw = th = tg = std::max(1, std::atoi(e));
+  // FMNMF_SPLITS="w,h,g,v" fixes the number of splits per pass (0 = automatic)
+  int fix[4] = {0, 0, 0, 0};
+  if (const char* e = std::getenv("FMNMF_SPLITS")) std::sscanf(e, "%d,%d,%d,%d", &fix[0], &fix[1], &fix[2], &fix[3]);
+  auto slots_for = [&](int i, int tiles, int dflt) { return fix[i] > 0 ? fix[i] * tiles : dflt; };
+  choose_split(nF, d->T, slots_for(0, nF, tw), 64, 16, &L->Sw, &L->tw);
+  choose_split(nT, d->F, slots_for(1, nT, th), 64, 16, &L->Sh, &L->fh);
+  choose_split(nF, d->T, slots_for(2, nF, tg), 64, 16, &L->Sg, &L->tg);
+  choose_split(nF, d->T, slots_for(3, nF, 16 * nF), 32, 64, &L->Sv, &L->tv);
   L->nll = cdiv(d->F, 16) * cdiv(d->T, 64);
   L->rb = d->precision == FMNMF_FP64 ? 8 : 4;
   const size_t rb = L->rb, cb = 2 * rb;

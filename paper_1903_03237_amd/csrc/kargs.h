@@ -43,7 +43,7 @@ struct KArgs {
   double* ll;
   void* Yd;  // optional [F][T][MP] y~ (derived output for error reports)
   int Sw, Sh, Sg, Sv;  // number of splits of each reduction
-  int tw, fh, tg, tv;  // frames (or bins) covered by one split; multiples of 64
+  int tw, fh, tg, tv;  // frames (or bins) covered by one split; multiples of 16 (tv: of 64)
 };
 
 }  // namespace fmnmf

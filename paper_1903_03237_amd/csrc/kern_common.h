@@ -191,6 +191,14 @@ __device__ __forceinline__ void load4(const typename P::R* __restrict__ p, int l
   }
 }
 
+// Orders this wavefront's LDS accesses around a point (stores before it are
+// visible to its loads after it); no other wavefront is involved.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Device-side error latch (vector-memory atomic on a global word).
 __device__ __forceinline__ void raise_status(int* st, int bit) { atomicOr(st, bit); }
 
