@@ -167,6 +167,49 @@ def cpu_baseline(X, init, delta, seconds):
             "avail_cores": len(os.sched_getaffinity(0)), "blas_threads": blas_threads}
 
 
+def serving_leg(torch, n_requests, precision, iters=100):
+    """Config-5 style serving: closed-loop capacity of the batched server, then
+    Poisson arrivals at 0.7 x that capacity through the batched server and
+    through the one-at-a-time path."""
+    from paper_1903_03237_amd import serve, synth
+
+    print(f"[bench] serving: generating base mixtures for {n_requests} requests", file=sys.stderr, flush=True)
+    bases = synth.serving_bases()
+    # the base mixtures stay resident; a request's mixture is a device crop
+    tdt = torch.complex128 if precision == "fp64" else torch.complex64
+    dbases = {M: torch.from_numpy(X).to("cuda:0", dtype=tdt) for M, X in bases.items()}
+    specs0 = synth.serving_specs(n_requests, None)
+    prep = {sp.rid: synth.serving_request(sp, bases) for sp in specs0}
+
+    def build(rate):
+        reqs = []
+        for sp in synth.serving_specs(n_requests, rate):
+            _, init, delta = prep[sp.rid]
+            X = dbases[sp.M][:, :sp.T, :]
+            reqs.append(serve.Request(sp.rid, sp.arrival, X, sp.N, sp.K, init, delta, iters))
+        return reqs
+
+    srv = serve.Server(precision=precision, hbm_budget=96 << 30, max_active=64, chunk=10,
+                       max_bins=int(os.environ.get("FMNMF_SERVE_MAX_BINS", 1_000_000)))
+    print("[bench] serving: closed loop (all requests at t = 0)", file=sys.stderr, flush=True)
+    closed = build(None)
+    cap = serve.summary(srv.run(closed), closed)
+    print("[bench] serving: closed loop, one at a time", file=sys.stderr, flush=True)
+    cap_seq = serve.summary(serve.run_sequential(closed, precision=precision), closed)
+    rate = 0.7 * cap["requests_per_s"]
+    reqs = build(rate)
+    print(f"[bench] serving: Poisson arrivals at {rate:.2f} requests/s, batched", file=sys.stderr, flush=True)
+    batched = serve.summary(srv.run(reqs), reqs)
+    print("[bench] serving: the same arrivals one at a time", file=sys.stderr, flush=True)
+    seq = serve.summary(serve.run_sequential(reqs, precision=precision), reqs)
+    torch.cuda.synchronize()
+    return {"requests": n_requests, "iters_per_request": iters, "precision": precision,
+            "workload": "M in {2,4,8}, N in {2..5}, K in {8,16,32}, F=513, T ~ U{200..4000}; "
+                        "crops of seeded base mixtures, seeded per-request initial states",
+            "closed_loop": cap, "closed_loop_one_at_a_time": cap_seq, "arrival_rate_per_s": rate, "batched": batched, "one_at_a_time": seq,
+            "p50_latency_s": batched["p50_latency_s"], "p99_latency_s": batched["p99_latency_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +218,8 @@ def main():
     ap.add_argument("--paths", default="bf16,fp32,fp64", help="precision paths to time; first is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="requests of the serving leg (0 disables it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -204,6 +249,10 @@ def main():
         print(f"[bench] timing {p}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
         res[p] = run_gpu(torch, fmnmf, X, init, delta, N, K, p, args.steps, args.warmup, cache)
     cache.clear()
+
+    serving = None
+    if args.serving_requests > 0:
+        serving = serving_leg(torch, args.serving_requests, paths[0])
 
     base = None
     if not args.no_cpu_baseline:
@@ -260,6 +309,8 @@ def main():
             ref = base["ll_step1"]
             e["ll_rel_err_step1"] = abs(r["ll_step1"] - ref) / max(abs(ref), F * T * M)
         out["paths"][p] = e
+    if serving is not None:
+        out["serving"] = serving
     if "fp64" in res and head != "fp64":
         out["speedup_vs_fp64"] = out["paths"][head]["iters_per_s"] / out["paths"]["fp64"]["iters_per_s"]
     if base is not None:

@@ -102,6 +102,21 @@ int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws
  * Returns only launch errors. */
 int fmnmf_step(fmnmf_ctx* c, int n_iter);
 
+/* Serving: enqueue n_iter >= 0 full iterations of each of the `count`
+ * distinct contexts cs[0..count-1] as batched launches; asynchronous.
+ * Contexts of one shape class (same precision, M class {1-2, 3-4, 5-8},
+ * N class {1-2, 3-4, 5-6, 7-8} and K class {1-16, 17-32, 33-64}) share a
+ * single launch of every kernel of the iteration, up to 16 per launch, so
+ * requests of different sizes fill the GPU together.  Results are those of
+ * fmnmf_step on each context alone (the per-context arithmetic is the same).
+ * All work is enqueued on the stream of cs[0]; that stream first waits for
+ * the work already enqueued on every other context's stream, and every other
+ * stream then waits for the batch, so later calls on any context are ordered
+ * after it.  One iteration of each distinct context list is captured as a
+ * HIP graph and cached (up to 8 lists; destroying a context drops the graphs
+ * that contain it).  Returns only validation and launch errors. */
+int fmnmf_step_batch(fmnmf_ctx* const* cs, int count, int n_iter);
+
 /* Synchronise the context's stream and return the log-likelihood of Eq. (17)
  * (without the constant -F T M log(pi)) after the last completed iteration
  * (L_0 right after fmnmf_init or fmnmf_set_state).  Every iteration leaves

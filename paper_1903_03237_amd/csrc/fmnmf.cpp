@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "kargs.h"
@@ -50,6 +51,7 @@ struct Layout {
   int MP, FP, TP, KP, K4, KPB, KT;
   int Sw, Sh, Sg, Sv, tw, fh, tg, tv, nll;
   size_t rb;  // bytes of one real element (FP64: 8, else 4)
+  size_t off_kdev;
   size_t off_Xt, off_W, off_H, off_G, off_Wb, off_Wtb, off_Hb, off_Htb, off_Q, off_Qr, off_Qinv, off_logdet,
       off_pw, off_ph, off_pg, off_pv, off_pll, off_status, off_ll, off_Yd, total;
 };
@@ -134,6 +136,7 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   L->off_status = take(8);
   L->off_ll = take(8);
   L->off_Yd = take((d->flags & FMNMF_WITH_DERIVED) ? F * T * MP * rb : 0);
+  L->off_kdev = take(sizeof(KArgs));
   L->total = align_up(off, 256);
 }
 
@@ -142,13 +145,14 @@ struct Ops {
   launch_fn wpass, hpass, gpass, vpass, proj, ip, logdet, qinv, mirror;
   hipError_t (*mu)(const KArgs&, int, hipStream_t);
   hipError_t (*wiener)(const KArgs&, void*, hipStream_t);
+  hipError_t (*batch)(int, const KArgs* const*, const KArgs* const*, int, hipStream_t);
 };
 #define FM_OPS(sfx)                                                                                       \
   Ops {                                                                                                   \
     fmnmf::launch_wpass_##sfx, fmnmf::launch_hpass_##sfx, fmnmf::launch_gpass_##sfx,                     \
         fmnmf::launch_vpass_##sfx, fmnmf::launch_proj_##sfx, fmnmf::launch_ip_##sfx,                     \
         fmnmf::launch_logdet_##sfx, fmnmf::launch_qinv_##sfx, fmnmf::launch_mirror_##sfx,               \
-        fmnmf::launch_mu_##sfx, fmnmf::launch_wiener_##sfx                                               \
+        fmnmf::launch_mu_##sfx, fmnmf::launch_wiener_##sfx, fmnmf::launch_batch_##sfx                     \
   }
 const Ops kOps[3] = {FM_OPS(f64), FM_OPS(f32), FM_OPS(bf16)};
 
@@ -163,6 +167,8 @@ struct fmnmf_ctx {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   bool graph_tried = false;
+  KArgs* kdev = nullptr;      // device copy of a (read by batched launches)
+  hipEvent_t ev = nullptr;    // joins this context's stream with a batch's stream
 };
 
 namespace {
@@ -300,9 +306,150 @@ int download(fmnmf_ctx* c, const void* src, size_t N, size_t R1, size_t R2, size
   return FMNMF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched iterations (serving).  Contexts are grouped by shape class
+// (precision, MP, NMAX, KT): the contexts of a class share one launch of
+// every kernel of the iteration (at most MAXB per launch).  One iteration of
+// a batch is captured once as a graph on the first context's stream and kept
+// in a small cache keyed by the exact list of contexts.
+// ---------------------------------------------------------------------------
+struct BatchGraph {
+  std::vector<fmnmf_ctx*> key;
+  hipStream_t s = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+};
+std::mutex g_batch_mu;
+std::vector<BatchGraph> g_batch;  // most recently used last
+constexpr size_t kBatchCache = 8;
+
+void free_batch_graph(BatchGraph& b) {
+  if (b.ge) (void)hipGraphExecDestroy(b.ge);
+  if (b.g) (void)hipGraphDestroy(b.g);
+  b.ge = nullptr;
+  b.g = nullptr;
+}
+
+void drop_batch_graphs(fmnmf_ctx* c) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (size_t i = 0; i < g_batch.size();) {
+    auto& k = g_batch[i].key;
+    if (std::find(k.begin(), k.end(), c) != k.end()) {
+      free_batch_graph(g_batch[i]);
+      g_batch.erase(g_batch.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
+
+// Launch order of one batched iteration: kernel by kernel, class by class.
+int enqueue_batch_iteration(fmnmf_ctx* const* cs, int count, hipStream_t s) {
+  struct Group {
+    int prec, mp, nmax, kt;
+    std::vector<int> idx;
+  };
+  std::vector<Group> groups;
+  for (int i = 0; i < count; ++i) {
+    const KArgs& a = cs[i]->a;
+    const int nmax = a.N <= 2 ? 2 : a.N <= 4 ? 4 : a.N <= 6 ? 6 : 8;
+    Group* g = nullptr;
+    for (auto& x : groups)
+      if (x.prec == cs[i]->d.precision && x.mp == a.MP && x.nmax == nmax && x.kt == a.KT &&
+          (int)x.idx.size() < fmnmf::MAXB_HOST)
+        g = &x;
+    if (!g) {
+      groups.push_back(Group{cs[i]->d.precision, a.MP, nmax, a.KT, {}});
+      g = &groups.back();
+    }
+    g->idx.push_back(i);
+  }
+  for (int k = 0; k < FMNMF_NUM_KERNELS; ++k) {
+    for (auto& g : groups) {
+      const KArgs* host[fmnmf::MAXB_HOST];
+      const KArgs* dev[fmnmf::MAXB_HOST];
+      const int n = (int)g.idx.size();
+      for (int j = 0; j < n; ++j) {
+        host[j] = &cs[g.idx[j]]->a;
+        dev[j] = cs[g.idx[j]]->kdev;
+      }
+      int rc = launch_check(kOps[g.prec].batch(k, host, dev, n, s), kKernelNames[k]);
+      if (rc) return rc;
+    }
+  }
+  return FMNMF_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int fmnmf_step_batch(fmnmf_ctx* const* cs, int count, int n_iter) {
+  if (!cs || count < 1) return fail(FMNMF_E_INVAL, "need at least one context");
+  if (n_iter < 0) return fail(FMNMF_E_INVAL, "n_iter < 0");
+  for (int i = 0; i < count; ++i) {
+    if (!cs[i]) return fail(FMNMF_E_INVAL, "context %d is NULL", i);
+    for (int j = 0; j < i; ++j)
+      if (cs[j] == cs[i]) return fail(FMNMF_E_INVAL, "context %d appears twice", i);
+  }
+  if (n_iter == 0) return FMNMF_OK;
+  hipStream_t s0 = cs[0]->s;
+  // the batch's stream waits for every context's earlier work ...
+  for (int i = 1; i < count; ++i)
+    if (cs[i]->s != s0) {
+      HIPCHK(hipEventRecord(cs[i]->ev, cs[i]->s));
+      HIPCHK(hipStreamWaitEvent(s0, cs[i]->ev, 0));
+    }
+  std::vector<fmnmf_ctx*> key(cs, cs + count);
+  hipGraphExec_t ge = nullptr;
+  const char* ng = std::getenv("FMNMF_NO_GRAPH");
+  const bool use_graph = s0 != nullptr && !(ng && ng[0] == '1');
+  if (use_graph) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (size_t i = 0; i < g_batch.size(); ++i)
+      if (g_batch[i].key == key && g_batch[i].s == s0) {
+        BatchGraph b = g_batch[i];
+        g_batch.erase(g_batch.begin() + i);
+        g_batch.push_back(b);
+        ge = b.ge;
+        break;
+      }
+    if (!ge && hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      int rc = enqueue_batch_iteration(cs, count, s0);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(s0, &g);
+      BatchGraph b;
+      if (rc == FMNMF_OK && e == hipSuccess && g && hipGraphInstantiate(&b.ge, g, nullptr, nullptr, 0) == hipSuccess) {
+        b.key = key;
+        b.s = s0;
+        b.g = g;
+        if (g_batch.size() >= kBatchCache) {
+          free_batch_graph(g_batch.front());
+          g_batch.erase(g_batch.begin());
+        }
+        g_batch.push_back(b);
+        ge = b.ge;
+      } else if (g) {
+        hipGraphDestroy(g);
+      }
+      (void)hipGetLastError();
+    }
+  }
+  for (int it = 0; it < n_iter; ++it) {
+    if (ge) {
+      HIPCHK(hipGraphLaunch(ge, s0));
+    } else {
+      int rc = enqueue_batch_iteration(cs, count, s0);
+      if (rc) return rc;
+    }
+  }
+  // ... and every context's stream waits for the batch
+  HIPCHK(hipEventRecord(cs[0]->ev, s0));
+  for (int i = 1; i < count; ++i)
+    if (cs[i]->s != s0) HIPCHK(hipStreamWaitEvent(cs[i]->s, cs[0]->ev, 0));
+  return FMNMF_OK;
+}
+
 
 size_t fmnmf_workspace_bytes(const fmnmf_dims* d) {
   if (check_dims(d) != FMNMF_OK) return 0;
@@ -386,10 +533,13 @@ int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws
   a.fh = L.fh;
   a.tg = L.tg;
   a.tv = L.tv;
+  c->kdev = reinterpret_cast<KArgs*>(ws + L.off_kdev);
   hipError_t e = hipMemsetAsync(ws_dev, 0, L.total, c->s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->kdev, &c->a, sizeof(KArgs), hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     delete c;
-    return fail(FMNMF_E_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+    return fail(FMNMF_E_HIP, "context set-up: %s", hipGetErrorString(e));
   }
   rc = upload_state(c, W0, H0, G0, Q0);
   if (rc) {
@@ -527,8 +677,10 @@ const char* fmnmf_kernel_name(int k) { return (k >= 0 && k < FMNMF_NUM_KERNELS) 
 
 void fmnmf_destroy(fmnmf_ctx* c) {
   if (!c) return;
+  drop_batch_graphs(c);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->ev) (void)hipEventDestroy(c->ev);
   delete c;
 }
 

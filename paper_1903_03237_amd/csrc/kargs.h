@@ -5,6 +5,9 @@
 
 namespace fmnmf {
 
+// Contexts per batched launch (the device-side table size).
+constexpr int MAXB_HOST = 16;
+
 // Bits of the device-side sticky status word.
 enum : int { ST_SINGULAR = 1, ST_NONFINITE = 2 };
 

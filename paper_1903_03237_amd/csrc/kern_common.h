@@ -199,6 +199,40 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ---------------------------------------------------------------------------
+// Block coordinates and batched launches.
+//
+// Every kernel body takes its block coordinates explicitly: (blockIdx.x,
+// blockIdx.y) of a plain launch, or the coordinates inside one context of a
+// batched launch.  A batched launch runs the same kernel for up to MAXB
+// contexts of one shape class in a single 1-D grid: context i owns linear
+// blocks [start[i], start[i+1]), laid out x-fastest over its own grid of
+// width gx[i]; its arguments are read from the device copy a[i] kept in the
+// context's workspace.
+// ---------------------------------------------------------------------------
+struct Blk {
+  int x, y;
+};
+
+constexpr int MAXB = MAXB_HOST;
+struct Batch {
+  const KArgs* a[MAXB];
+  int start[MAXB + 1];
+  int gx[MAXB];
+  int n;
+};
+
+__device__ __forceinline__ const KArgs& batch_block(const Batch& B, Blk& blk) {
+  const int lin = blockIdx.x;
+  int i = 0;
+  for (int j = 1; j < B.n; ++j)
+    if (lin >= B.start[j]) i = j;
+  const int r = lin - B.start[i];
+  blk.x = r % B.gx[i];
+  blk.y = r / B.gx[i];
+  return *B.a[i];
+}
+
 // Device-side error latch (vector-memory atomic on a global word).
 __device__ __forceinline__ void raise_status(int* st, int bit) { atomicOr(st, bit); }
 

@@ -24,7 +24,7 @@ OK, E_INVAL, E_UNSUPPORTED, E_WORKSPACE, E_HIP, E_SINGULAR, E_NONFINITE = 0, -1,
 EXPORTS = ("fmnmf_workspace_bytes", "fmnmf_footprint_bytes", "fmnmf_init", "fmnmf_step",
            "fmnmf_loglik", "fmnmf_separate", "fmnmf_get_state", "fmnmf_set_state",
            "fmnmf_get_derived", "fmnmf_destroy", "fmnmf_last_error", "fmnmf_profile_step",
-           "fmnmf_kernel_name")
+           "fmnmf_kernel_name", "fmnmf_step_batch")
 KERNELS = ("wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g", "vpass", "ip", "proj")
 
 
@@ -59,6 +59,8 @@ def lib():
     L.fmnmf_footprint_bytes.restype = sz
     L.fmnmf_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Dims), vp, vp, sz, dp, dp, dp, dp, vp]
     L.fmnmf_step.argtypes = [vp, ctypes.c_int]
+    L.fmnmf_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int]
+    L.fmnmf_step_batch.restype = ctypes.c_int
     L.fmnmf_loglik.argtypes = [vp, dp]
     L.fmnmf_separate.argtypes = [vp, vp]
     L.fmnmf_get_state.argtypes = [vp, dp, dp, dp, dp]
@@ -108,6 +110,15 @@ def _f64c(a) -> np.ndarray:
 def _q_as_f64(Q) -> np.ndarray:
     q = np.ascontiguousarray(np.asarray(Q, dtype=np.complex128))
     return q.view(np.float64)
+
+
+def step_batch(models, n: int = 1):
+    """Enqueue n iterations of every model in `models` as batched launches
+    (fmnmf_step_batch): work goes on the first model's stream; the others'
+    streams are joined before and after."""
+    ms = list(models)
+    arr = (ctypes.c_void_p * len(ms))(*[m._ctx.value for m in ms])
+    _check(lib().fmnmf_step_batch(arr, len(ms), int(n)))
 
 
 class FastMNMF:

@@ -126,3 +126,46 @@ def random_problem(F: int, T: int, M: int, N: int, K: int, *, seed: int,
         Q0 = Q0 + 0.3 * _cn(rng, (F, M, M))
         G0 = G0 * rng.uniform(0.5, 1.5, size=G0.shape)
     return X, (W0, H0, G0, Q0), delta_for(X, delta_rel)
+
+
+# ----------------------------------------------------------------------------
+# Serving workload: many requests of different shapes arriving over time.
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ServingSpec:
+    """One request of the serving workload (no data yet)."""
+    rid: int
+    arrival: float  # seconds after the start of the run
+    M: int
+    N: int
+    K: int
+    T: int
+
+
+def serving_specs(n: int, rate: float | None, *, seed: int = SEED_BASE + 5000,
+                  Ms=(2, 4, 8), Ns=(2, 3, 4, 5), Ks=(8, 16, 32), T_range=(200, 4000)):
+    """n request shapes drawn uniformly from the given sets, T ~ U{T_range};
+    Poisson arrivals at `rate` requests/s (all at t = 0 when rate is None)."""
+    rng = np.random.default_rng(seed)  # shapes: the same whatever the rate
+    shapes = [(int(rng.choice(Ms)), int(rng.choice(Ns)), int(rng.choice(Ks)),
+               int(rng.integers(T_range[0], T_range[1] + 1))) for _ in range(n)]
+    arr = np.random.default_rng(seed + 1)
+    gaps = arr.exponential(1.0 / rate, size=n) if rate else np.zeros(n)
+    t = np.cumsum(gaps) - gaps[0]
+    return [ServingSpec(i, float(t[i]), *shapes[i]) for i in range(n)]
+
+
+def serving_bases(F: int = 513, T: int = 4000, Ms=(2, 4, 8), *, seed: int = SEED_BASE + 6000):
+    """One seeded base mixture per microphone count (3 NMF-structured sources,
+    Wishart SCMs with dof = 2M); requests use crops of these."""
+    return {M: make_mixture(F, T, M, 3, 16, dof=2 * M, seed=seed + M, gain=True) for M in Ms}
+
+
+def serving_request(spec: ServingSpec, bases, *, seed: int = SEED_BASE + 7000, delta_rel: float = 1e-8):
+    """(X [F, T, M], init, delta) of a request: the first T frames of the base
+    mixture for its M (a view, no copy), with its own seeded initial state."""
+    X = bases[spec.M][:, :spec.T, :]
+    F = X.shape[0]
+    init = make_init(F, spec.T, spec.M, spec.N, spec.K, seed=seed + spec.rid)
+    return X, init, delta_for(X, delta_rel)

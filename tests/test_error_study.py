@@ -43,10 +43,12 @@ def _study(device, X, init, delta, N, K, iters, precisions):
     s = fm.State(*init)
     states = [s]
     L = [fm.loglik(X, s, delta)]
-    for _ in range(iters):
+    for i in range(iters):
         s = fm.step(X, s, delta)
         states.append(s)
         L.append(fm.loglik(X, s, delta))
+        if (i + 1) % 10 == 0:
+            print(f"oracle step {i + 1}/{iters}", flush=True)
     lam = fm.psd(s.W, s.H)
     xt_ref, yt_ref = fm.project(X, s.Q), fm.model(lam, s.G, delta)
     sep_ref = fm.separate(X, s, delta)
@@ -55,6 +57,7 @@ def _study(device, X, init, delta, N, K, iters, precisions):
         Xd = torch.from_numpy(np.ascontiguousarray(X.astype(np.complex64))).to(device)
         m = fmnmf.FastMNMF(Xd, N, K, init, precision=p, delta=delta, derived=True)
         # per-step error from injected oracle states
+        print(f"{p}: per-step errors", flush=True)
         step_err = []
         for i in range(iters):
             m.set_state(states[i].W, states[i].H, states[i].G, states[i].Q)
