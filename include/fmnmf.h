@@ -61,7 +61,13 @@ enum fmnmf_precision {
 };
 
 enum fmnmf_flags {
-  FMNMF_WITH_DERIVED = 4u /* reserve device memory for y~ so fmnmf_get_derived(.., 1, ..) works */
+  FMNMF_NORMALIZE = 1u,    /* after the IP update, rescale the redundant scales of the model without
+                              changing Eq. (17): phi_f = (1/M) sum_ij |Q_f,ij|^2, Q_f /= sqrt(phi_f),
+                              g~_nf. /= phi_f; mu_nf = sum_m g~_nfm, g~_nf. /= mu_nf, w_n.f *= mu_nf;
+                              nu_nk = sum_f w_nkf, w_nk. /= nu_nk, h_nk. *= nu_nk (not in the paper) */
+  FMNMF_TIE_G_OVER_F = 2u, /* frequency-independent g~_nm: the numerator and denominator of Eq. (21)
+                              are also summed over f (every g~_nf. gets the same factor) */
+  FMNMF_WITH_DERIVED = 4u  /* reserve device memory for y~ so fmnmf_get_derived(.., 1, ..) works */
 };
 
 /* Problem description.
@@ -152,6 +158,7 @@ enum fmnmf_kernel {
   FMNMF_K_MU_G,      /* G~ multiplicative update                                */
   FMNMF_K_VPASS,     /* V_fm accumulation (Eq. 18), split partials              */
   FMNMF_K_IP,        /* V_fm, IP solve + normalisation + log-det (Eqs. 18-20)   */
+  FMNMF_K_NORM,      /* scale normalisation of W and H (FMNMF_NORMALIZE only)   */
   FMNMF_K_PROJ,      /* x~ = |Q x|^2 and per-block likelihood terms (Eq. 17)    */
   FMNMF_NUM_KERNELS
 };

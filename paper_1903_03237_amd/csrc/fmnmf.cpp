@@ -63,7 +63,8 @@ int check_dims(const fmnmf_dims* d) {
   if (d->precision < FMNMF_FP64 || d->precision > FMNMF_MIXED_BF16)
     return fail(FMNMF_E_INVAL, "unknown precision %d", d->precision);
   if (!(d->delta >= 0.0) || !std::isfinite(d->delta)) return fail(FMNMF_E_INVAL, "delta must be finite and >= 0");
-  if ((d->flags & ~(unsigned)FMNMF_WITH_DERIVED) != 0u) return fail(FMNMF_E_INVAL, "unknown flags 0x%x", d->flags);
+  if ((d->flags & ~(unsigned)(FMNMF_WITH_DERIVED | FMNMF_NORMALIZE | FMNMF_TIE_G_OVER_F)) != 0u)
+    return fail(FMNMF_E_INVAL, "unknown flags 0x%x", d->flags);
   if (d->M > 8) return fail(FMNMF_E_UNSUPPORTED, "M = %d > 8 microphones is not built", d->M);
   if (d->N > 8) return fail(FMNMF_E_UNSUPPORTED, "N = %d > 8 sources is not built", d->N);
   if (d->K > 64) return fail(FMNMF_E_UNSUPPORTED, "K = %d > 64 bases is not built", d->K);
@@ -142,7 +143,7 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
 
 typedef hipError_t (*launch_fn)(const KArgs&, hipStream_t);
 struct Ops {
-  launch_fn wpass, hpass, gpass, vpass, proj, ip, logdet, qinv, mirror;
+  launch_fn wpass, hpass, gpass, vpass, proj, ip, logdet, qinv, mirror, norm;
   hipError_t (*mu)(const KArgs&, int, hipStream_t);
   hipError_t (*wiener)(const KArgs&, void*, hipStream_t);
   hipError_t (*batch)(int, const KArgs* const*, const KArgs* const*, int, hipStream_t);
@@ -152,6 +153,7 @@ struct Ops {
     fmnmf::launch_wpass_##sfx, fmnmf::launch_hpass_##sfx, fmnmf::launch_gpass_##sfx,                     \
         fmnmf::launch_vpass_##sfx, fmnmf::launch_proj_##sfx, fmnmf::launch_ip_##sfx,                     \
         fmnmf::launch_logdet_##sfx, fmnmf::launch_qinv_##sfx, fmnmf::launch_mirror_##sfx,               \
+        fmnmf::launch_norm_##sfx,                                                                         \
         fmnmf::launch_mu_##sfx, fmnmf::launch_wiener_##sfx, fmnmf::launch_batch_##sfx                     \
   }
 const Ops kOps[3] = {FM_OPS(f64), FM_OPS(f32), FM_OPS(bf16)};
@@ -182,7 +184,7 @@ int launch_check(hipError_t e, const char* what) {
 int enqueue_proj_ll(fmnmf_ctx* c) { return launch_check(c->ops->proj(c->a, c->s), "proj"); }
 
 const char* const kKernelNames[FMNMF_NUM_KERNELS] = {"wpass", "mu_w", "hpass", "mu_h", "gpass",
-                                                     "mu_g",  "vpass", "ip",    "proj"};
+                                                     "mu_g",  "vpass", "ip",    "norm",  "proj"};
 
 hipError_t launch_kernel(fmnmf_ctx* c, int k) {
   const Ops& o = *c->ops;
@@ -192,9 +194,10 @@ hipError_t launch_kernel(fmnmf_ctx* c, int k) {
     case FMNMF_K_HPASS: return o.hpass(c->a, c->s);
     case FMNMF_K_MU_H: return o.mu(c->a, 1, c->s);
     case FMNMF_K_GPASS: return o.gpass(c->a, c->s);
-    case FMNMF_K_MU_G: return o.mu(c->a, 2, c->s);
+    case FMNMF_K_MU_G: return o.mu(c->a, c->a.tieg ? 3 : 2, c->s);
     case FMNMF_K_VPASS: return o.vpass(c->a, c->s);
     case FMNMF_K_IP: return o.ip(c->a, c->s);
+    case FMNMF_K_NORM: return c->a.norm ? o.norm(c->a, c->s) : hipSuccess;
     case FMNMF_K_PROJ: return o.proj(c->a, c->s);
   }
   return hipErrorInvalidValue;
@@ -346,7 +349,7 @@ void drop_batch_graphs(fmnmf_ctx* c) {
 // Launch order of one batched iteration: kernel by kernel, class by class.
 int enqueue_batch_iteration(fmnmf_ctx* const* cs, int count, hipStream_t s) {
   struct Group {
-    int prec, mp, nmax, kt;
+    int prec, mp, nmax, kt, norm, tieg;
     std::vector<int> idx;
   };
   std::vector<Group> groups;
@@ -355,11 +358,11 @@ int enqueue_batch_iteration(fmnmf_ctx* const* cs, int count, hipStream_t s) {
     const int nmax = a.N <= 2 ? 2 : a.N <= 4 ? 4 : a.N <= 6 ? 6 : 8;
     Group* g = nullptr;
     for (auto& x : groups)
-      if (x.prec == cs[i]->d.precision && x.mp == a.MP && x.nmax == nmax && x.kt == a.KT &&
-          (int)x.idx.size() < fmnmf::MAXB_HOST)
+      if (x.prec == cs[i]->d.precision && x.mp == a.MP && x.nmax == nmax && x.kt == a.KT && x.norm == a.norm &&
+          x.tieg == a.tieg && (int)x.idx.size() < fmnmf::MAXB_HOST)
         g = &x;
     if (!g) {
-      groups.push_back(Group{cs[i]->d.precision, a.MP, nmax, a.KT, {}});
+      groups.push_back(Group{cs[i]->d.precision, a.MP, nmax, a.KT, a.norm, a.tieg, {}});
       g = &groups.back();
     }
     g->idx.push_back(i);
@@ -502,6 +505,8 @@ int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws
   a.KPB = L.KPB;
   a.KT = L.KT;
   a.delta = d->delta;
+  a.norm = (d->flags & FMNMF_NORMALIZE) ? 1 : 0;
+  a.tieg = (d->flags & FMNMF_TIE_G_OVER_F) ? 1 : 0;
   a.X = X_dev;
   a.Xt = ws + L.off_Xt;
   a.W = ws + L.off_W;

@@ -23,6 +23,7 @@ struct KArgs {
   int MP, FP, TP;  // M padded to a power of two; F, T padded to multiples of 32
   int KP, K4, KPB, KT;  // W/H rows (16*KT), K rounded to 4, bf16 depth (32-multiple), 16-wide k tiles
   double delta;         // additive floor of y~
+  int norm, tieg;       // FMNMF_NORMALIZE, FMNMF_TIE_G_OVER_F
   const void* X;
   void* Xt;
   void* W;

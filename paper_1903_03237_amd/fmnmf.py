@@ -18,14 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libfmnmf.so")
 
 FP64, FP32, MIXED_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "mixed": MIXED_BF16}
-WITH_DERIVED = 4
+NORMALIZE, TIE_G_OVER_F, WITH_DERIVED = 1, 2, 4
 
 OK, E_INVAL, E_UNSUPPORTED, E_WORKSPACE, E_HIP, E_SINGULAR, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
 EXPORTS = ("fmnmf_workspace_bytes", "fmnmf_footprint_bytes", "fmnmf_init", "fmnmf_step",
            "fmnmf_loglik", "fmnmf_separate", "fmnmf_get_state", "fmnmf_set_state",
            "fmnmf_get_derived", "fmnmf_destroy", "fmnmf_last_error", "fmnmf_profile_step",
            "fmnmf_kernel_name", "fmnmf_step_batch")
-KERNELS = ("wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g", "vpass", "ip", "proj")
+KERNELS = ("wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g", "vpass", "ip", "norm", "proj")
 
 
 class Dims(ctypes.Structure):
@@ -128,10 +128,11 @@ class FastMNMF:
              "fp64", complex64 for "fp32" / "bf16"); borrowed for the
              lifetime of the object.
     init     (W0 [N,K,F], H0 [N,K,T], G0 [N,F,M], Q0 [F,M,M] complex) host arrays.
+    normalize / tie_g  the FMNMF_NORMALIZE / FMNMF_TIE_G_OVER_F options.
     """
 
     def __init__(self, X, N: int, K: int, init, precision="fp64", delta=0.0,
-                 derived=False, stream=None):
+                 derived=False, stream=None, normalize=False, tie_g=False):
         import torch
 
         F, T, M = X.shape
@@ -139,7 +140,8 @@ class FastMNMF:
         want = torch.complex128 if p == FP64 else torch.complex64
         if X.dtype != want or not X.is_cuda or not X.is_contiguous():
             raise ValueError(f"X must be a contiguous {want} HIP tensor")
-        self.dims = make_dims(F, T, M, N, K, p, delta, WITH_DERIVED if derived else 0)
+        flags = (WITH_DERIVED if derived else 0) | (NORMALIZE if normalize else 0) | (TIE_G_OVER_F if tie_g else 0)
+        self.dims = make_dims(F, T, M, N, K, p, delta, flags)
         self.precision = p
         self.shape = (F, T, M, N, K)
         self.X = X

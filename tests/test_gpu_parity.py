@@ -153,3 +153,52 @@ def test_reduced_precision_one_step(device, precision, tol_ll, tol_state, case):
     Y = m.separate().cpu().numpy()
     assert _rel(Y, fm.separate(X, s4, delta)) < tol_state
     m.close()
+
+
+# Options: the frequency-tied G~ (Eq. 21 summed over f) and the scale
+# normalisation, each against the oracle's step with the same option.
+@pytest.mark.parametrize("tie_g,norm", [(True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("case", [(21, 37, 3, 2, 5), (50, 64, 8, 6, 40), (33, 90, 4, 3, 16)],
+                         ids=lambda c: "F%dT%dM%dN%dK%d" % c)
+def test_fp64_options_parity(device, case, tie_g, norm):
+    F, T, M, N, K = case
+    X, init, delta = synth.random_problem(F, T, M, N, K, seed=F * 11 + T, delta_rel=1e-8, random_q=True)
+    if tie_g:  # the tied variant starts from a frequency-independent g~
+        init = (init[0], init[1], np.broadcast_to(init[2][:, :1, :], init[2].shape).copy(), init[3])
+    import torch
+
+    from paper_1903_03237_amd import fmnmf
+
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).to(device)
+    m = fmnmf.FastMNMF(Xd, N, K, init, precision="fp64", delta=delta, tie_g=tie_g, normalize=norm)
+    s = fm.State(*init)
+    for _ in range(3):
+        m.step(1)
+        s = fm.step(X, s, delta, tie_g=tie_g, norm=norm)
+        L = fm.loglik(X, s, delta)
+        assert abs(m.loglik() - L) <= 1e-10 * abs(L)
+    W, H, G, Q = m.get_state()
+    for a, b in ((W, s.W), (H, s.H), (G, s.G), (Q, s.Q)):
+        assert _rel(a, b) < 1e-10
+    if tie_g:
+        assert np.ptp(G, axis=1).max() <= 1e-12 * np.abs(G).max()
+    m.close()
+
+
+def test_options_reduced_precision(device):
+    # the options on the FP32 and mixed paths: L within the per-step bound
+    F, T, M, N, K = 50, 200, 8, 5, 32
+    X, init, delta = synth.random_problem(F, T, M, N, K, seed=77, delta_rel=1e-8, random_q=True)
+    init = (init[0], init[1], np.broadcast_to(init[2][:, :1, :], init[2].shape).copy(), init[3])
+    import torch
+
+    from paper_1903_03237_amd import fmnmf
+
+    s1 = fm.step(X, fm.State(*init), delta, tie_g=True, norm=True)
+    L1 = fm.loglik(X, s1, delta)
+    for p, tol in (("fp32", 1e-5), ("bf16", 5e-4)):
+        Xd = torch.from_numpy(np.ascontiguousarray(X.astype(np.complex64))).to(device)
+        m = fmnmf.FastMNMF(Xd, N, K, init, precision=p, delta=delta, tie_g=True, normalize=True)
+        m.step(1)
+        assert abs(m.loglik() - L1) <= tol * max(abs(L1), F * T * M), p
+        m.close()
