@@ -657,6 +657,7 @@ int fmnmf_profile_step(fmnmf_ctx* c, int n_iter, double* ms) {
   int rc = FMNMF_OK;
   for (int i = 0; i < n_iter && rc == FMNMF_OK; ++i)
     for (int k = 0; k < FMNMF_NUM_KERNELS && rc == FMNMF_OK; ++k) {
+      if (k == FMNMF_K_NORM && !c->a.norm) continue;  // not part of this context's iteration
       hipEvent_t* p = &ev[2 * ((size_t)i * FMNMF_NUM_KERNELS + k)];
       if (hipEventRecord(p[0], c->s) != hipSuccess) rc = fail(FMNMF_E_HIP, "hipEventRecord failed");
       else if ((rc = launch_check(launch_kernel(c, k), kKernelNames[k])) == FMNMF_OK &&
@@ -668,6 +669,7 @@ int fmnmf_profile_step(fmnmf_ctx* c, int n_iter, double* ms) {
   if (rc == FMNMF_OK)
     for (int i = 0; i < n_iter; ++i)
       for (int k = 0; k < FMNMF_NUM_KERNELS; ++k) {
+        if (k == FMNMF_K_NORM && !c->a.norm) continue;
         float t = 0.f;
         hipEvent_t* p = &ev[2 * ((size_t)i * FMNMF_NUM_KERNELS + k)];
         if (hipEventElapsedTime(&t, p[0], p[1]) == hipSuccess) ms[k] += t / n_iter;
