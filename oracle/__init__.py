@@ -12,8 +12,10 @@ fastmnmf   the method itself, step by step in the paper's order and notation
            (Sec. III-A/B: Eqs. (9), (17)-(21), (23)-(24)), plus the
            multichannel Wiener filter of Eq. (3) in the jointly
            diagonalised form obtained by substituting Eq. (16).
+fastfca    FastFCA (Sec. III-C): the same spatial model and IP step with the
+           unconstrained source model, lambda updated by Eq. (22).
 fullrank   brute-force companions on explicit M x M matrices (Eqs. (1)-(4),
            (10)-(11)) used to pin the fast formulas on tiny inputs.
 """
 
-from . import fastmnmf, fullrank  # noqa: F401
+from . import fastfca, fastmnmf, fullrank  # noqa: F401

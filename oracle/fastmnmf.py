@@ -141,8 +141,13 @@ def terms_G(Xt, s: State, delta: float = 0.0, tie_over_f: bool = False):
     ``tie_over_f`` gives the frequency-independent variant g~_nm: both sums
     are also taken over f (and broadcast back over f).  Not the paper's default.
     """
-    lam = psd(s.W, s.H)
-    Yt = model(lam, s.G, delta)
+    return terms_G_psd(Xt, psd(s.W, s.H), s.G, delta, tie_over_f)
+
+
+def terms_G_psd(Xt, lam, G, delta: float = 0.0, tie_over_f: bool = False):
+    """The sums of Eq. (21) for any source model lambda [F, T, N] (NMF or
+    unconstrained): sum_t lambda x~/y~^2 and sum_t lambda/y~, each [N, F, M]."""
+    Yt = model(lam, G, delta)
     num = np.einsum("ftn,ftm->nfm", lam, Xt / Yt ** 2, optimize=True)
     den = np.einsum("ftn,ftm->nfm", lam, 1.0 / Yt, optimize=True)
     if tie_over_f:
@@ -283,12 +288,16 @@ def separate(X: np.ndarray, s: State, delta: float = 0.0) -> np.ndarray:
         x^_ftn = Q_f^-1 Diag(lambda_ftn g~_nf / y~_ft) Q_f x_ft.
     Returns [N, F, T, M] complex128.
     """
-    lam = psd(s.W, s.H)  # [F, T, N]
-    Yt = model(lam, s.G, delta)  # [F, T, M]
-    Qinv = np.linalg.inv(s.Q)  # [F, M, M]
-    Z = np.einsum("fmj,ftj->ftm", s.Q, X, optimize=True)  # Q_f x_ft
-    out = np.empty((s.W.shape[0],) + X.shape, dtype=np.complex128)
-    for n in range(s.W.shape[0]):
-        gain = lam[:, :, n, None] * s.G[n][:, None, :] / Yt  # [F, T, M]
+    return separate_psd(X, psd(s.W, s.H), s.G, s.Q, delta)
+
+
+def separate_psd(X: np.ndarray, lam: np.ndarray, G: np.ndarray, Q: np.ndarray, delta: float = 0.0) -> np.ndarray:
+    """The filter of ``separate`` for any source model lambda [F, T, N]."""
+    Yt = model(lam, G, delta)  # [F, T, M]
+    Qinv = np.linalg.inv(Q)  # [F, M, M]
+    Z = np.einsum("fmj,ftj->ftm", Q, X, optimize=True)  # Q_f x_ft
+    out = np.empty((G.shape[0],) + X.shape, dtype=np.complex128)
+    for n in range(G.shape[0]):
+        gain = lam[:, :, n, None] * G[n][:, None, :] / Yt  # [F, T, M]
         out[n] = np.einsum("fij,ftj->fti", Qinv, gain * Z, optimize=True)
     return out

@@ -128,6 +128,28 @@ def random_problem(F: int, T: int, M: int, N: int, K: int, *, seed: int,
     return X, (W0, H0, G0, Q0), delta_for(X, delta_rel)
 
 
+def make_fca_init(F: int, T: int, M: int, N: int, *, seed: int):
+    """Initial state of the unconstrained source model (FastFCA):
+    (lam0 [N,F,T] ~ U[0.1, 1), G0 [N,F,M] = 1/M, Q0 = I)."""
+    rng = np.random.default_rng(seed)
+    lam0 = rng.uniform(0.1, 1.0, size=(N, F, T))
+    G0 = np.full((N, F, M), 1.0 / M)
+    Q0 = np.broadcast_to(np.eye(M, dtype=np.complex128), (F, M, M)).copy()
+    return lam0, G0, Q0
+
+
+def random_fca_problem(F: int, T: int, M: int, N: int, *, seed: int, dof: int | None = None,
+                       delta_rel: float = 0.0, random_q: bool = False):
+    """random_problem for FastFCA: mixture + (lam0 [N,F,T], G0, Q0) + delta."""
+    X = make_mixture(F, T, M, N, 2, dof=dof or max(2 * M, 2), seed=seed, gain=True)
+    lam0, G0, Q0 = make_fca_init(F, T, M, N, seed=seed + 500)
+    if random_q:
+        rng = np.random.default_rng(seed + 777)
+        Q0 = Q0 + 0.3 * _cn(rng, (F, M, M))
+        G0 = G0 * rng.uniform(0.5, 1.5, size=G0.shape)
+    return X, (lam0, G0, Q0), delta_for(X, delta_rel)
+
+
 # ----------------------------------------------------------------------------
 # Serving workload: many requests of different shapes arriving over time.
 # ----------------------------------------------------------------------------
