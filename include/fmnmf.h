@@ -17,6 +17,13 @@
  * The model is y~_ftm = sum_n lambda_ftn g~_nfm + delta with a caller-chosen
  * constant floor delta >= 0 (delta = 0 is the paper's model).
  *
+ * With the flag FMNMF_FCA the same library runs FastFCA (Sec. III-C): the
+ * spatial model, the G~ update and the IP step are unchanged, and the NMF
+ * source model is replaced by the unconstrained one, every lambda_ftn a free
+ * parameter updated by Eq. (22).  One step is then
+ *   lambda update (Eq. 22) -> G~ update (Eq. 21) -> IP (Eqs. 18-20)
+ *   -> projection and log-likelihood (Eq. 17).
+ *
  * Conventions for every entry point:
  *   - Every function returns FMNMF_OK (0) or a negative FMNMF_E_* code and
  *     never throws.  fmnmf_last_error() gives a thread-local message for the
@@ -67,12 +74,16 @@ enum fmnmf_flags {
                               nu_nk = sum_f w_nkf, w_nk. /= nu_nk, h_nk. *= nu_nk (not in the paper) */
   FMNMF_TIE_G_OVER_F = 2u, /* frequency-independent g~_nm: the numerator and denominator of Eq. (21)
                               are also summed over f (every g~_nf. gets the same factor) */
-  FMNMF_WITH_DERIVED = 4u  /* reserve device memory for y~ so fmnmf_get_derived(.., 1, ..) works */
+  FMNMF_WITH_DERIVED = 4u, /* reserve device memory for y~ so fmnmf_get_derived(.., 1, ..) works */
+  FMNMF_FCA = 8u           /* FastFCA: unconstrained lambda_ftn updated by Eq. (22) instead of
+                              W and H (K must be 0; FMNMF_FP64 or FMNMF_FP32 only, not with
+                              FMNMF_NORMALIZE); W0 / W carry lambda as [N][F][T], H0 / H are NULL */
 };
 
 /* Problem description.
  *   F >= 1 frequency bins, T >= 1 frames, 1 <= M <= 8 microphones,
- *   1 <= N <= 8 sources, 1 <= K <= 64 NMF bases, precision (enum above),
+ *   1 <= N <= 8 sources, 1 <= K <= 64 NMF bases (K = 0 with FMNMF_FCA),
+ *   precision (enum above),
  *   flags (enum above), delta >= 0 finite (additive floor of y~). */
 typedef struct {
   int F, T, M, N, K;
@@ -95,7 +106,8 @@ size_t fmnmf_footprint_bytes(const fmnmf_dims* d);
  *   ws_dev  device workspace of ws_bytes >= fmnmf_workspace_bytes(d) bytes,
  *           256-byte aligned; lent to the context until fmnmf_destroy.
  *   W0, H0, G0  host FP64 initial parameters [N][K][F], [N][K][T], [N][F][M],
- *           all > 0 (copied).
+ *           all > 0 (copied).  With FMNMF_FCA, W0 is lambda_0 [N][F][T] > 0
+ *           and H0 must be NULL.
  *   Q0      host FP64 interleaved complex [F][M][M], row m of Q_f = q_fm^H,
  *           each Q_f non-singular (copied).
  *   stream  hipStream_t on which all work of the context is enqueued
@@ -104,14 +116,16 @@ size_t fmnmf_footprint_bytes(const fmnmf_dims* d);
 int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws_dev, size_t ws_bytes,
                const double* W0, const double* H0, const double* G0, const double* Q0, void* stream);
 
-/* Enqueue n_iter >= 0 full iterations (W, H, G~, Q, x~, L); asynchronous.
+/* Enqueue n_iter >= 0 full iterations (W, H, G~, Q, x~, L; with FMNMF_FCA
+ * lambda, G~, Q, x~, L); asynchronous.
  * Returns only launch errors. */
 int fmnmf_step(fmnmf_ctx* c, int n_iter);
 
 /* Serving: enqueue n_iter >= 0 full iterations of each of the `count`
  * distinct contexts cs[0..count-1] as batched launches; asynchronous.
  * Contexts of one shape class (same precision, M class {1-2, 3-4, 5-8},
- * N class {1-2, 3-4, 5-6, 7-8} and K class {1-16, 17-32, 33-64}) share a
+ * N class {1-2, 3-4, 5-6, 7-8} and K class {0 (FMNMF_FCA), 1-16, 17-32,
+ * 33-64}, and the same FMNMF_NORMALIZE / FMNMF_TIE_G_OVER_F flags) share a
  * single launch of every kernel of the iteration, up to 16 per launch, so
  * requests of different sizes fill the GPU together.  Results are those of
  * fmnmf_step on each context alone (the per-context arithmetic is the same).
@@ -135,20 +149,25 @@ int fmnmf_loglik(fmnmf_ctx* c, double* ll);
  * synchronises. */
 int fmnmf_separate(fmnmf_ctx* c, void* Y_dev);
 
-/* Copy the current parameters to host FP64 arrays (layouts as fmnmf_init);
- * any pointer may be NULL to skip it; synchronises. */
+/* Copy the current parameters to host FP64 arrays (layouts as fmnmf_init;
+ * with FMNMF_FCA, W receives lambda [N][F][T] and H must be NULL); any pointer
+ * may be NULL to skip it; synchronises. */
 int fmnmf_get_state(fmnmf_ctx* c, double* W, double* H, double* G, double* Q);
 
-/* Replace all parameters from host FP64 arrays (layouts as fmnmf_init), then
- * enqueue the projection and log-likelihood of the new state. */
+/* Replace all parameters from host FP64 arrays (layouts as fmnmf_init; with
+ * FMNMF_FCA, W is lambda [N][F][T] and H must be NULL), then enqueue the
+ * projection and log-likelihood of the new state. */
 int fmnmf_set_state(fmnmf_ctx* c, const double* W, const double* H, const double* G, const double* Q);
 
 /* Copy a derived [F][T][M] tensor to host FP64 memory; synchronises.
  *   which = 0: x~ of the current Q (definition under Eq. 17);
- *   which = 1: y~ of the current W, H, G~ (needs FMNMF_WITH_DERIVED). */
+ *   which = 1: y~ of the current lambda and G~ (needs FMNMF_WITH_DERIVED). */
 int fmnmf_get_derived(fmnmf_ctx* c, int which, double* out);
 
-/* Kernels of one iteration, in launch order, for fmnmf_profile_step. */
+/* Kernels of one iteration, for fmnmf_profile_step.  The launch order is
+ * FMNMF_K_LAM, then FMNMF_K_WPASS .. FMNMF_K_PROJ; a context runs either
+ * FMNMF_K_LAM (FMNMF_FCA) or the four W / H kernels, and FMNMF_K_NORM only
+ * with FMNMF_NORMALIZE. */
 enum fmnmf_kernel {
   FMNMF_K_WPASS = 0, /* W numerators/denominators (Eq. 23), split partials       */
   FMNMF_K_MU_W,      /* W multiplicative update                                 */
@@ -160,6 +179,7 @@ enum fmnmf_kernel {
   FMNMF_K_IP,        /* V_fm, IP solve + normalisation + log-det (Eqs. 18-20)   */
   FMNMF_K_NORM,      /* scale normalisation of W and H (FMNMF_NORMALIZE only)   */
   FMNMF_K_PROJ,      /* x~ = |Q x|^2 and per-block likelihood terms (Eq. 17)    */
+  FMNMF_K_LAM,       /* lambda update of the unconstrained model (Eq. 22)       */
   FMNMF_NUM_KERNELS
 };
 

@@ -53,19 +53,27 @@ struct Layout {
   size_t rb;  // bytes of one real element (FP64: 8, else 4)
   size_t off_kdev;
   size_t off_Qi64;
+  size_t off_Lam;
   size_t off_Xt, off_W, off_H, off_G, off_Wb, off_Wtb, off_Hb, off_Htb, off_Q, off_Qr, off_Qinv, off_logdet,
       off_pw, off_ph, off_pg, off_pv, off_pll, off_status, off_ll, off_Yd, total;
 };
 
 int check_dims(const fmnmf_dims* d) {
   if (!d) return fail(FMNMF_E_INVAL, "dims is NULL");
-  if (d->F < 1 || d->T < 1 || d->M < 1 || d->N < 1 || d->K < 1)
-    return fail(FMNMF_E_INVAL, "F, T, M, N, K must be >= 1 (got %d %d %d %d %d)", d->F, d->T, d->M, d->N, d->K);
+  const bool fca = (d->flags & FMNMF_FCA) != 0u;
+  if (d->F < 1 || d->T < 1 || d->M < 1 || d->N < 1)
+    return fail(FMNMF_E_INVAL, "F, T, M, N must be >= 1 (got %d %d %d %d)", d->F, d->T, d->M, d->N);
+  if (fca ? d->K != 0 : d->K < 1)
+    return fail(FMNMF_E_INVAL, fca ? "K must be 0 with FMNMF_FCA (got %d)" : "K must be >= 1 (got %d)", d->K);
   if (d->precision < FMNMF_FP64 || d->precision > FMNMF_MIXED_BF16)
     return fail(FMNMF_E_INVAL, "unknown precision %d", d->precision);
   if (!(d->delta >= 0.0) || !std::isfinite(d->delta)) return fail(FMNMF_E_INVAL, "delta must be finite and >= 0");
-  if ((d->flags & ~(unsigned)(FMNMF_WITH_DERIVED | FMNMF_NORMALIZE | FMNMF_TIE_G_OVER_F)) != 0u)
+  if ((d->flags & ~(unsigned)(FMNMF_WITH_DERIVED | FMNMF_NORMALIZE | FMNMF_TIE_G_OVER_F | FMNMF_FCA)) != 0u)
     return fail(FMNMF_E_INVAL, "unknown flags 0x%x", d->flags);
+  if (fca && d->precision == FMNMF_MIXED_BF16)
+    return fail(FMNMF_E_UNSUPPORTED, "FMNMF_FCA has no bf16 contractions: use FMNMF_FP32 or FMNMF_FP64");
+  if (fca && (d->flags & FMNMF_NORMALIZE))
+    return fail(FMNMF_E_UNSUPPORTED, "FMNMF_NORMALIZE is not built for FMNMF_FCA");
   if (d->M > 8) return fail(FMNMF_E_UNSUPPORTED, "M = %d > 8 microphones is not built", d->M);
   if (d->N > 8) return fail(FMNMF_E_UNSUPPORTED, "N = %d > 8 sources is not built", d->N);
   if (d->K > 64) return fail(FMNMF_E_UNSUPPORTED, "K = %d > 64 bases is not built", d->K);
@@ -87,7 +95,8 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   L->MP = d->M <= 2 ? 2 : d->M <= 4 ? 4 : 8;
   L->FP = round_up(d->F, 32);
   L->TP = round_up(d->T, 32);
-  L->KT = d->K <= 16 ? 1 : d->K <= 32 ? 2 : 4;
+  const bool fca = (d->flags & FMNMF_FCA) != 0u;
+  L->KT = fca ? 0 : d->K <= 16 ? 1 : d->K <= 32 ? 2 : 4;
   L->KP = 16 * L->KT;
   L->K4 = round_up(d->K, 4);
   L->KPB = round_up(L->KP, 32);
@@ -122,6 +131,7 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   L->off_W = take(N * KP * FP * rb);
   L->off_H = take(N * KP * TP * rb);
   L->off_G = take(N * FP * MP * rb);
+  L->off_Lam = take(fca ? N * FP * TP * rb : 0);
   L->off_Wb = take(bf ? N * KP * FP * 2 : 0);
   L->off_Wtb = take(bf ? N * FP * KPB * 2 : 0);
   L->off_Hb = take(bf ? N * KP * TP * 2 : 0);
@@ -145,7 +155,7 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
 
 typedef hipError_t (*launch_fn)(const KArgs&, hipStream_t);
 struct Ops {
-  launch_fn wpass, hpass, gpass, vpass, proj, ip, logdet, qinv, mirror, norm;
+  launch_fn wpass, hpass, gpass, vpass, proj, ip, logdet, qinv, mirror, norm, lampass;
   hipError_t (*mu)(const KArgs&, int, hipStream_t);
   hipError_t (*wiener)(const KArgs&, void*, hipStream_t);
   hipError_t (*batch)(int, const KArgs* const*, const KArgs* const*, int, hipStream_t);
@@ -155,7 +165,7 @@ struct Ops {
     fmnmf::launch_wpass_##sfx, fmnmf::launch_hpass_##sfx, fmnmf::launch_gpass_##sfx,                     \
         fmnmf::launch_vpass_##sfx, fmnmf::launch_proj_##sfx, fmnmf::launch_ip_##sfx,                     \
         fmnmf::launch_logdet_##sfx, fmnmf::launch_qinv_##sfx, fmnmf::launch_mirror_##sfx,               \
-        fmnmf::launch_norm_##sfx,                                                                         \
+        fmnmf::launch_norm_##sfx, fmnmf::launch_lampass_##sfx,                                            \
         fmnmf::launch_mu_##sfx, fmnmf::launch_wiener_##sfx, fmnmf::launch_batch_##sfx                     \
   }
 const Ops kOps[3] = {FM_OPS(f64), FM_OPS(f32), FM_OPS(bf16)};
@@ -185,11 +195,25 @@ int launch_check(hipError_t e, const char* what) {
 // x~ and the likelihood partials of the current state.
 int enqueue_proj_ll(fmnmf_ctx* c) { return launch_check(c->ops->proj(c->a, c->s), "proj"); }
 
-const char* const kKernelNames[FMNMF_NUM_KERNELS] = {"wpass", "mu_w", "hpass", "mu_h", "gpass",
-                                                     "mu_g",  "vpass", "ip",    "norm",  "proj"};
+const char* const kKernelNames[FMNMF_NUM_KERNELS] = {"wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g",
+                                                     "vpass", "ip",   "norm",  "proj", "lam"};
+
+// Launch order of one iteration, and whether kernel k belongs to the
+// iteration of a context: the lambda pass (FastFCA) or the W / H kernels
+// (NMF source model), the normalisation only when asked for.
+const int kOrder[FMNMF_NUM_KERNELS] = {FMNMF_K_LAM,   FMNMF_K_WPASS, FMNMF_K_MU_W, FMNMF_K_HPASS,
+                                       FMNMF_K_MU_H,  FMNMF_K_GPASS, FMNMF_K_MU_G, FMNMF_K_VPASS,
+                                       FMNMF_K_IP,    FMNMF_K_NORM,  FMNMF_K_PROJ};
+bool in_iteration(const KArgs& a, int k) {
+  if (k == FMNMF_K_LAM) return a.fca != 0;
+  if (k <= FMNMF_K_MU_H) return a.fca == 0;
+  if (k == FMNMF_K_NORM) return a.norm != 0;
+  return true;
+}
 
 hipError_t launch_kernel(fmnmf_ctx* c, int k) {
   const Ops& o = *c->ops;
+  if (!in_iteration(c->a, k)) return hipSuccess;
   switch (k) {
     case FMNMF_K_WPASS: return o.wpass(c->a, c->s);
     case FMNMF_K_MU_W: return o.mu(c->a, 0, c->s);
@@ -201,13 +225,15 @@ hipError_t launch_kernel(fmnmf_ctx* c, int k) {
     case FMNMF_K_IP: return o.ip(c->a, c->s);
     case FMNMF_K_NORM: return c->a.norm ? o.norm(c->a, c->s) : hipSuccess;
     case FMNMF_K_PROJ: return o.proj(c->a, c->s);
+    case FMNMF_K_LAM: return c->a.fca ? o.lampass(c->a, c->s) : hipSuccess;
   }
   return hipErrorInvalidValue;
 }
 
-// One full iteration (Eqs. 23, 24, 21, 18-20, 17).
+// One full iteration (Eqs. 23, 24, 21, 18-20, 17; FastFCA: Eqs. 22, 21, 18-20, 17).
 int enqueue_iteration(fmnmf_ctx* c) {
-  for (int k = 0; k < FMNMF_NUM_KERNELS; ++k) {
+  for (int k : kOrder) {
+    if (!in_iteration(c->a, k)) continue;
     int rc = launch_check(launch_kernel(c, k), kKernelNames[k]);
     if (rc) return rc;
   }
@@ -234,9 +260,17 @@ int upload_state(fmnmf_ctx* c, const double* W, const double* H, const double* G
   const fmnmf_dims& d = c->d;
   const Layout& L = c->L;
   const size_t N = d.N, K = d.K, F = d.F, T = d.T, M = d.M, MP = L.MP, FP = L.FP, TP = L.TP, KP = L.KP;
-  if (!W || !H || !G || !Q) return fail(FMNMF_E_INVAL, "state pointers must not be NULL");
-  if (!finite_positive(W, N * K * F) || !finite_positive(H, N * K * T) || !finite_positive(G, N * F * M))
-    return fail(FMNMF_E_INVAL, "W, H and G must be finite and > 0");
+  const bool fca = c->a.fca != 0;
+  if (fca) {  // W carries lambda [N][F][T]; there is no H
+    if (!W || !G || !Q) return fail(FMNMF_E_INVAL, "lambda (W), G and Q must not be NULL");
+    if (H) return fail(FMNMF_E_INVAL, "H must be NULL with FMNMF_FCA");
+    if (!finite_positive(W, N * F * T) || !finite_positive(G, N * F * M))
+      return fail(FMNMF_E_INVAL, "lambda and G must be finite and > 0");
+  } else {
+    if (!W || !H || !G || !Q) return fail(FMNMF_E_INVAL, "state pointers must not be NULL");
+    if (!finite_positive(W, N * K * F) || !finite_positive(H, N * K * T) || !finite_positive(G, N * F * M))
+      return fail(FMNMF_E_INVAL, "W, H and G must be finite and > 0");
+  }
   for (size_t i = 0; i < 2 * F * M * M; ++i)
     if (!std::isfinite(Q[i])) return fail(FMNMF_E_INVAL, "Q must be finite");
   const bool f64 = d.precision == FMNMF_FP64;
@@ -257,18 +291,27 @@ int upload_state(fmnmf_ctx* c, const double* W, const double* H, const double* G
     return FMNMF_OK;
   };
   int rc;
-  rc = put(c->a.W, N * KP * FP, [&](double* h) {
-    for (size_t n = 0; n < N; ++n)
-      for (size_t k = 0; k < K; ++k)
-        for (size_t f = 0; f < F; ++f) h[(n * KP + k) * FP + f] = W[(n * K + k) * F + f];
-  });
-  if (rc) return rc;
-  rc = put(c->a.H, N * KP * TP, [&](double* h) {
-    for (size_t n = 0; n < N; ++n)
-      for (size_t k = 0; k < K; ++k)
-        for (size_t t = 0; t < T; ++t) h[(n * KP + k) * TP + t] = H[(n * K + k) * T + t];
-  });
-  if (rc) return rc;
+  if (fca) {
+    rc = put(c->a.Lam, N * FP * TP, [&](double* h) {
+      for (size_t n = 0; n < N; ++n)
+        for (size_t f = 0; f < F; ++f)
+          for (size_t t = 0; t < T; ++t) h[(n * FP + f) * TP + t] = W[(n * F + f) * T + t];
+    });
+    if (rc) return rc;
+  } else {
+    rc = put(c->a.W, N * KP * FP, [&](double* h) {
+      for (size_t n = 0; n < N; ++n)
+        for (size_t k = 0; k < K; ++k)
+          for (size_t f = 0; f < F; ++f) h[(n * KP + k) * FP + f] = W[(n * K + k) * F + f];
+    });
+    if (rc) return rc;
+    rc = put(c->a.H, N * KP * TP, [&](double* h) {
+      for (size_t n = 0; n < N; ++n)
+        for (size_t k = 0; k < K; ++k)
+          for (size_t t = 0; t < T; ++t) h[(n * KP + k) * TP + t] = H[(n * K + k) * T + t];
+    });
+    if (rc) return rc;
+  }
   rc = put(c->a.G, N * FP * MP, [&](double* h) {
     for (size_t n = 0; n < N; ++n)
       for (size_t f = 0; f < F; ++f)
@@ -369,7 +412,7 @@ int enqueue_batch_iteration(fmnmf_ctx* const* cs, int count, hipStream_t s) {
     }
     g->idx.push_back(i);
   }
-  for (int k = 0; k < FMNMF_NUM_KERNELS; ++k) {
+  for (int k : kOrder) {
     for (auto& g : groups) {
       const KArgs* host[fmnmf::MAXB_HOST];
       const KArgs* dev[fmnmf::MAXB_HOST];
@@ -509,11 +552,13 @@ int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws
   a.delta = d->delta;
   a.norm = (d->flags & FMNMF_NORMALIZE) ? 1 : 0;
   a.tieg = (d->flags & FMNMF_TIE_G_OVER_F) ? 1 : 0;
+  a.fca = (d->flags & FMNMF_FCA) ? 1 : 0;
   a.X = X_dev;
   a.Xt = ws + L.off_Xt;
   a.W = ws + L.off_W;
   a.H = ws + L.off_H;
   a.G = ws + L.off_G;
+  a.Lam = a.fca ? static_cast<void*>(ws + L.off_Lam) : nullptr;
   const bool bf = d->precision == FMNMF_MIXED_BF16;
   a.Wb = bf ? reinterpret_cast<__bf16*>(ws + L.off_Wb) : nullptr;
   a.Wtb = bf ? reinterpret_cast<__bf16*>(ws + L.off_Wtb) : nullptr;
@@ -621,8 +666,13 @@ int fmnmf_get_state(fmnmf_ctx* c, double* W, double* H, double* G, double* Q) {
   const fmnmf_dims& d = c->d;
   const Layout& L = c->L;
   int rc;
-  if (W && (rc = download(c, c->a.W, d.N, d.K, d.F, L.KP, L.FP, W))) return rc;
-  if (H && (rc = download(c, c->a.H, d.N, d.K, d.T, L.KP, L.TP, H))) return rc;
+  if (c->a.fca) {
+    if (H) return fail(FMNMF_E_INVAL, "H must be NULL with FMNMF_FCA");
+    if (W && (rc = download(c, c->a.Lam, d.N, d.F, d.T, L.FP, L.TP, W))) return rc;
+  } else {
+    if (W && (rc = download(c, c->a.W, d.N, d.K, d.F, L.KP, L.FP, W))) return rc;
+    if (H && (rc = download(c, c->a.H, d.N, d.K, d.T, L.KP, L.TP, H))) return rc;
+  }
   if (G && (rc = download(c, c->a.G, d.N, d.F, d.M, L.FP, L.MP, G))) return rc;
   if (Q) {
     std::vector<double> h(2 * (size_t)d.F * L.MP * L.MP);
@@ -659,8 +709,9 @@ int fmnmf_profile_step(fmnmf_ctx* c, int n_iter, double* ms) {
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   int rc = FMNMF_OK;
   for (int i = 0; i < n_iter && rc == FMNMF_OK; ++i)
-    for (int k = 0; k < FMNMF_NUM_KERNELS && rc == FMNMF_OK; ++k) {
-      if (k == FMNMF_K_NORM && !c->a.norm) continue;  // not part of this context's iteration
+    for (int j = 0; j < FMNMF_NUM_KERNELS && rc == FMNMF_OK; ++j) {
+      const int k = kOrder[j];
+      if (!in_iteration(c->a, k)) continue;
       hipEvent_t* p = &ev[2 * ((size_t)i * FMNMF_NUM_KERNELS + k)];
       if (hipEventRecord(p[0], c->s) != hipSuccess) rc = fail(FMNMF_E_HIP, "hipEventRecord failed");
       else if ((rc = launch_check(launch_kernel(c, k), kKernelNames[k])) == FMNMF_OK &&
@@ -672,7 +723,7 @@ int fmnmf_profile_step(fmnmf_ctx* c, int n_iter, double* ms) {
   if (rc == FMNMF_OK)
     for (int i = 0; i < n_iter; ++i)
       for (int k = 0; k < FMNMF_NUM_KERNELS; ++k) {
-        if (k == FMNMF_K_NORM && !c->a.norm) continue;
+        if (!in_iteration(c->a, k)) continue;
         float t = 0.f;
         hipEvent_t* p = &ev[2 * ((size_t)i * FMNMF_NUM_KERNELS + k)];
         if (hipEventElapsedTime(&t, p[0], p[1]) == hipSuccess) ms[k] += t / n_iter;

@@ -17,18 +17,21 @@ enum : int { ST_SINGULAR = 1, ST_NONFINITE = 2 };
 //   W    [N][KP][FP]  H [N][KP][TP]  G [N][FP][MP]           real
 //   Wb   [N][KP][FP]  Wtb [N][FP][KPB]  Hb [N][KP][TP]  Htb [N][TP][KPB]  bf16 mirrors
 //   Q    [F][MP][MP]  complex FP64 master;  Qr / Qinv [FP][MP][MP] complex R
+//   Lam  [N][FP][TP]  lambda of the unconstrained source model (FastFCA only;
+//                     K = 0 and KT = 0 then, W / H and their partials are empty)
 // Padded rows / columns (k >= K, f >= F, t >= T, m >= M) hold zeros.
 struct KArgs {
   int F, T, M, N, K;
   int MP, FP, TP;  // M padded to a power of two; F, T padded to multiples of 32
   int KP, K4, KPB, KT;  // W/H rows (16*KT), K rounded to 4, bf16 depth (32-multiple), 16-wide k tiles
   double delta;         // additive floor of y~
-  int norm, tieg;       // FMNMF_NORMALIZE, FMNMF_TIE_G_OVER_F
+  int norm, tieg, fca;  // FMNMF_NORMALIZE, FMNMF_TIE_G_OVER_F, FMNMF_FCA
   const void* X;
   void* Xt;
   void* W;
   void* H;
   void* G;
+  void* Lam;
   __bf16* Wb;
   __bf16* Wtb;
   __bf16* Hb;

@@ -13,6 +13,7 @@ namespace fmnmf {
   hipError_t launch_gpass_##sfx(const KArgs& a, hipStream_t s);             \
   hipError_t launch_vpass_##sfx(const KArgs& a, hipStream_t s);             \
   hipError_t launch_proj_##sfx(const KArgs& a, hipStream_t s);              \
+  hipError_t launch_lampass_##sfx(const KArgs& a, hipStream_t s);           \
   hipError_t launch_wiener_##sfx(const KArgs& a, void* out, hipStream_t s); \
   hipError_t launch_ip_##sfx(const KArgs& a, hipStream_t s);                \
   hipError_t launch_norm_##sfx(const KArgs& a, hipStream_t s);              \

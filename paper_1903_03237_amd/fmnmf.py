@@ -18,14 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libfmnmf.so")
 
 FP64, FP32, MIXED_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": MIXED_BF16, "mixed": MIXED_BF16}
-NORMALIZE, TIE_G_OVER_F, WITH_DERIVED = 1, 2, 4
+NORMALIZE, TIE_G_OVER_F, WITH_DERIVED, FCA = 1, 2, 4, 8
 
 OK, E_INVAL, E_UNSUPPORTED, E_WORKSPACE, E_HIP, E_SINGULAR, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
 EXPORTS = ("fmnmf_workspace_bytes", "fmnmf_footprint_bytes", "fmnmf_init", "fmnmf_step",
            "fmnmf_loglik", "fmnmf_separate", "fmnmf_get_state", "fmnmf_set_state",
            "fmnmf_get_derived", "fmnmf_destroy", "fmnmf_last_error", "fmnmf_profile_step",
            "fmnmf_kernel_name", "fmnmf_step_batch")
-KERNELS = ("wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g", "vpass", "ip", "norm", "proj")
+KERNELS = ("wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g", "vpass", "ip", "norm", "proj", "lam")
 
 
 class Dims(ctypes.Structure):
@@ -86,7 +86,9 @@ def _check(rc: int):
         raise FmnmfError(rc, lib().fmnmf_last_error().decode())
 
 
-def _dp(a: np.ndarray):
+def _dp(a):
+    if a is None:
+        return ctypes.POINTER(ctypes.c_double)()
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
@@ -133,6 +135,10 @@ class FastMNMF:
 
     def __init__(self, X, N: int, K: int, init, precision="fp64", delta=0.0,
                  derived=False, stream=None, normalize=False, tie_g=False):
+        flags = (WITH_DERIVED if derived else 0) | (NORMALIZE if normalize else 0) | (TIE_G_OVER_F if tie_g else 0)
+        self._open(X, N, K, init, precision, delta, flags, stream)
+
+    def _open(self, X, N, K, init, precision, delta, flags, stream):
         import torch
 
         F, T, M = X.shape
@@ -140,7 +146,6 @@ class FastMNMF:
         want = torch.complex128 if p == FP64 else torch.complex64
         if X.dtype != want or not X.is_cuda or not X.is_contiguous():
             raise ValueError(f"X must be a contiguous {want} HIP tensor")
-        flags = (WITH_DERIVED if derived else 0) | (NORMALIZE if normalize else 0) | (TIE_G_OVER_F if tie_g else 0)
         self.dims = make_dims(F, T, M, N, K, p, delta, flags)
         self.precision = p
         self.shape = (F, T, M, N, K)
@@ -155,7 +160,7 @@ class FastMNMF:
         self._ctx = ctypes.c_void_p()
         _check(lib().fmnmf_init(ctypes.byref(self._ctx), ctypes.byref(self.dims),
                                 ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
-                                nbytes, _dp(_f64c(W0)), _dp(_f64c(H0)), _dp(_f64c(G0)),
+                                nbytes, _dp(_f64c(W0)), _dp(None if H0 is None else _f64c(H0)), _dp(_f64c(G0)),
                                 _dp(_q_as_f64(Q0)), ctypes.c_void_p(self.stream.cuda_stream)))
 
     # -- iteration ---------------------------------------------------------
@@ -218,3 +223,28 @@ class FastMNMF:
             self.close()
         except Exception:
             pass
+
+
+class FastFCA(FastMNMF):
+    """FastFCA (flag FMNMF_FCA): the unconstrained source model, lambda [N, F, T]
+    updated by Eq. (22), with the same spatial model and IP step.
+
+    init     (lam0 [N,F,T], G0 [N,F,M], Q0 [F,M,M] complex) host arrays.
+    """
+
+    def __init__(self, X, N: int, init, precision="fp64", delta=0.0, derived=False, stream=None,
+                 tie_g=False):
+        lam0, G0, Q0 = init
+        flags = FCA | (WITH_DERIVED if derived else 0) | (TIE_G_OVER_F if tie_g else 0)
+        self._open(X, N, 0, (lam0, None, G0, Q0), precision, delta, flags, stream)
+
+    def get_state(self):
+        F, T, M, N, _ = self.shape
+        lam = np.empty((N, F, T))
+        G = np.empty((N, F, M))
+        Q = np.empty((F, M, M), dtype=np.complex128)
+        _check(lib().fmnmf_get_state(self._ctx, _dp(lam), _dp(None), _dp(G), _dp(Q.view(np.float64))))
+        return lam, G, Q
+
+    def set_state(self, lam, G, Q):
+        _check(lib().fmnmf_set_state(self._ctx, _dp(_f64c(lam)), _dp(None), _dp(_f64c(G)), _dp(_q_as_f64(Q))))

@@ -60,3 +60,25 @@ def test_null_arguments_are_rejected(L):
     v = ctypes.c_double()
     assert L.fmnmf_loglik(None, ctypes.byref(v)) == fmnmf.E_INVAL
     L.fmnmf_destroy(None)
+
+
+def test_kernel_names_match_the_binding(L):
+    assert [L.fmnmf_kernel_name(k).decode() for k in range(len(fmnmf.KERNELS))] == list(fmnmf.KERNELS)
+    assert L.fmnmf_kernel_name(len(fmnmf.KERNELS)) is None
+
+
+def test_fca_dims_validation_without_gpu(L):
+    F, T, M, N = 65, 300, 4, 3
+    fca = fmnmf.make_dims(F, T, M, N, 0, "fp32", flags=fmnmf.FCA)
+    nmf = fmnmf.make_dims(F, T, M, N, 4, "fp32")
+    b = fmnmf.workspace_bytes(fca)
+    assert b >= F * T * M * 4 + N * F * T * 4  # x~ and lambda
+    assert b != fmnmf.workspace_bytes(nmf)
+    assert fmnmf.workspace_bytes(fmnmf.make_dims(F, T, M, N, 0, "fp64", flags=fmnmf.FCA)) > b
+    for K, prec, flags, msg in [(4, "fp32", fmnmf.FCA, "K must be 0"),
+                                (0, "fp32", 0, "K must be >= 1"),
+                                (0, "bf16", fmnmf.FCA, "bf16"),
+                                (0, "fp32", fmnmf.FCA | fmnmf.NORMALIZE, "NORMALIZE")]:
+        assert fmnmf.workspace_bytes(fmnmf.make_dims(F, T, M, N, K, prec, flags=flags)) == 0
+        assert msg in L.fmnmf_last_error().decode()
+    assert fmnmf.workspace_bytes(fmnmf.make_dims(F, T, M, N, 0, "fp64", flags=fmnmf.FCA | fmnmf.TIE_G_OVER_F)) > 0
