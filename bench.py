@@ -137,6 +137,33 @@ def run_gpu(torch, fmnmf, X, init, delta, N, K, precision, steps, warmup, out_ca
     return {"elapsed": elapsed, "ll_end": ll, "wiener_ms": wiener_ms, "kernels_ms": kms, "ll_step1": ll1}
 
 
+def fca_leg(torch, fmnmf, synth, X, delta, N, precision, steps, warmup):
+    """FastFCA (unconstrained lambda, Eq. 22) on the same mixture: iterations/s
+    and the lambda pass against the HBM roofline."""
+    F, T, M = X.shape
+    rb = 8 if precision == "fp64" else 4
+    dt = np.complex128 if precision == "fp64" else np.complex64
+    Xd = torch.from_numpy(np.ascontiguousarray(X.astype(dt))).to("cuda:0")
+    init = synth.make_fca_init(F, T, M, N, seed=synth.SEED_BASE + 3600)
+    m = fmnmf.FastFCA(Xd, N, init, precision=precision, delta=delta)
+    m.step(warmup)
+    m.loglik()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kms = m.profile(5)
+    m.close()
+    del Xd
+    lam_bytes = F * T * (M + 2 * N) * rb  # x~ and lambda in, lambda out
+    ach = lam_bytes / (kms["lam"] * 1e-3) / 1e9
+    return {"iters_per_s": steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+            "kernels_ms": {k: round(v, 5) for k, v in kms.items() if v > 0},
+            "lam_pass": {"bound": "hbm", "algorithmic_bytes": lam_bytes, "achieved": ach, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}}
+
+
 def cpu_baseline(X, init, delta, seconds):
     from oracle import fastmnmf as fm
 
@@ -220,6 +247,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests of the serving leg (0 disables it)")
+    ap.add_argument("--fca-paths", default="fp32,fp64",
+                    help="precision paths of the FastFCA leg on the same mixture (empty disables it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -249,6 +278,10 @@ def main():
         print(f"[bench] timing {p}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
         res[p] = run_gpu(torch, fmnmf, X, init, delta, N, K, p, args.steps, args.warmup, cache)
     cache.clear()
+    fca = {}
+    for p in [q.strip() for q in args.fca_paths.split(",") if q.strip()]:
+        print(f"[bench] FastFCA {p}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
+        fca[p] = fca_leg(torch, fmnmf, synth, X, delta, N, p, args.steps, args.warmup)
 
     serving = None
     if args.serving_requests > 0:
@@ -309,6 +342,8 @@ def main():
             ref = base["ll_step1"]
             e["ll_rel_err_step1"] = abs(r["ll_step1"] - ref) / max(abs(ref), F * T * M)
         out["paths"][p] = e
+    if fca:
+        out["fastfca"] = fca
     if serving is not None:
         out["serving"] = serving
     if "fp64" in res and head != "fp64":
