@@ -236,6 +236,24 @@ def normalize(s: State) -> State:
 
 
 # ----------------------------------------------------------------------------
+# The paper's initialisation of the spatial model (Sec. IV-A)
+# ----------------------------------------------------------------------------
+
+def init_from_scm(X: np.ndarray, N: int):
+    """G_1f = (1/T) sum_t x_ft x_ft^H (average observed SCM), G_nf = I for
+    n >= 2; Q_f and g~ from the spectral decomposition G_1f = U Diag(e) U^H:
+    Q_f = U^H (rows by ascending eigenvalue), g~_1f = e, g~_nf = 1.
+    Returns (G [N, F, M], Q [F, M, M])."""
+    F, T, M = X.shape
+    R = np.einsum("fti,ftj->fij", X, X.conj(), optimize=True) / T
+    e, U = np.linalg.eigh(R)  # ascending eigenvalues, eigenvectors in columns
+    Q = np.conj(np.swapaxes(U, 1, 2))
+    G = np.ones((N, F, M))
+    G[0] = e
+    return G, Q
+
+
+# ----------------------------------------------------------------------------
 # One full iteration and a run
 # ----------------------------------------------------------------------------
 
