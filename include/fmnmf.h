@@ -159,6 +159,21 @@ int fmnmf_get_state(fmnmf_ctx* c, double* W, double* H, double* G, double* Q);
  * projection and log-likelihood of the new state. */
 int fmnmf_set_state(fmnmf_ctx* c, const double* W, const double* H, const double* G, const double* Q);
 
+/* The paper's initialisation of the spatial model (Sec. IV-A), computed on
+ * the device from X: the SCM of source 1 is the average observed SCM
+ * R_f = (1/T) sum_t x_ft x_ft^H, those of sources 2..N are the identity, and
+ * Q_f and G~ come from the spectral decomposition R_f = U_f Diag(e_f) U_f^H,
+ * which diagonalises all of them at once (Eq. 16):
+ *   Q_f = U_f^H, rows in ascending order of e_f;  g~_1f = e_f;  g~_nf = 1.
+ * Replaces Q and G~ of the context (W, H, or lambda with FMNMF_FCA, are
+ * kept) and enqueues the projection and log-likelihood of the new state;
+ * asynchronous.  The eigen-decomposition is FP64 cyclic Jacobi; each row of
+ * Q_f is determined up to a unit complex factor, which leaves x~, Eq. (17)
+ * and every later update unchanged.  An R_f with an eigenvalue not above
+ * 1e-13 times its largest (singular to working accuracy, e.g. T < M) latches
+ * FMNMF_E_SINGULAR. */
+int fmnmf_init_scm(fmnmf_ctx* c);
+
 /* Copy a derived [F][T][M] tensor to host FP64 memory; synchronises.
  *   which = 0: x~ of the current Q (definition under Eq. 17);
  *   which = 1: y~ of the current lambda and G~ (needs FMNMF_WITH_DERIVED). */

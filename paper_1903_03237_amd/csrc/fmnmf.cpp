@@ -155,7 +155,7 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
 
 typedef hipError_t (*launch_fn)(const KArgs&, hipStream_t);
 struct Ops {
-  launch_fn wpass, hpass, gpass, vpass, proj, ip, logdet, qinv, mirror, norm, lampass;
+  launch_fn wpass, hpass, gpass, vpass, proj, ip, logdet, qinv, mirror, norm, lampass, init_scm;
   hipError_t (*mu)(const KArgs&, int, hipStream_t);
   hipError_t (*wiener)(const KArgs&, void*, hipStream_t);
   hipError_t (*batch)(int, const KArgs* const*, const KArgs* const*, int, hipStream_t);
@@ -165,7 +165,7 @@ struct Ops {
     fmnmf::launch_wpass_##sfx, fmnmf::launch_hpass_##sfx, fmnmf::launch_gpass_##sfx,                     \
         fmnmf::launch_vpass_##sfx, fmnmf::launch_proj_##sfx, fmnmf::launch_ip_##sfx,                     \
         fmnmf::launch_logdet_##sfx, fmnmf::launch_qinv_##sfx, fmnmf::launch_mirror_##sfx,               \
-        fmnmf::launch_norm_##sfx, fmnmf::launch_lampass_##sfx,                                            \
+        fmnmf::launch_norm_##sfx, fmnmf::launch_lampass_##sfx, fmnmf::launch_init_scm_##sfx,              \
         fmnmf::launch_mu_##sfx, fmnmf::launch_wiener_##sfx, fmnmf::launch_batch_##sfx                     \
   }
 const Ops kOps[3] = {FM_OPS(f64), FM_OPS(f32), FM_OPS(bf16)};
@@ -686,6 +686,14 @@ int fmnmf_get_state(fmnmf_ctx* c, double* W, double* H, double* G, double* Q) {
         }
   }
   return sync_status(c);
+}
+
+int fmnmf_init_scm(fmnmf_ctx* c) {
+  if (!c) return fail(FMNMF_E_INVAL, "ctx is NULL");
+  int rc;
+  if ((rc = launch_check(c->ops->init_scm(c->a, c->s), "init_scm"))) return rc;
+  if ((rc = launch_check(c->ops->logdet(c->a, c->s), "logdet"))) return rc;
+  return enqueue_proj_ll(c);
 }
 
 int fmnmf_set_state(fmnmf_ctx* c, const double* W, const double* H, const double* G, const double* Q) {

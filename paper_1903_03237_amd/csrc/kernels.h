@@ -19,6 +19,7 @@ namespace fmnmf {
   hipError_t launch_norm_##sfx(const KArgs& a, hipStream_t s);              \
   hipError_t launch_logdet_##sfx(const KArgs& a, hipStream_t s);           \
   hipError_t launch_qinv_##sfx(const KArgs& a, hipStream_t s);             \
+  hipError_t launch_init_scm_##sfx(const KArgs& a, hipStream_t s);         \
   hipError_t launch_mirror_##sfx(const KArgs& a, hipStream_t s);           \
   hipError_t launch_mu_##sfx(const KArgs& a, int which, hipStream_t s);     \
   hipError_t launch_batch_##sfx(int kernel, const KArgs* const* host, const KArgs* const* dev, int n, hipStream_t s);

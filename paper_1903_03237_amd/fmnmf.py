@@ -24,7 +24,7 @@ OK, E_INVAL, E_UNSUPPORTED, E_WORKSPACE, E_HIP, E_SINGULAR, E_NONFINITE = 0, -1,
 EXPORTS = ("fmnmf_workspace_bytes", "fmnmf_footprint_bytes", "fmnmf_init", "fmnmf_step",
            "fmnmf_loglik", "fmnmf_separate", "fmnmf_get_state", "fmnmf_set_state",
            "fmnmf_get_derived", "fmnmf_destroy", "fmnmf_last_error", "fmnmf_profile_step",
-           "fmnmf_kernel_name", "fmnmf_step_batch")
+           "fmnmf_kernel_name", "fmnmf_step_batch", "fmnmf_init_scm")
 KERNELS = ("wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g", "vpass", "ip", "norm", "proj", "lam")
 
 
@@ -62,6 +62,8 @@ def lib():
     L.fmnmf_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int]
     L.fmnmf_step_batch.restype = ctypes.c_int
     L.fmnmf_loglik.argtypes = [vp, dp]
+    L.fmnmf_init_scm.argtypes = [vp]
+    L.fmnmf_init_scm.restype = ctypes.c_int
     L.fmnmf_separate.argtypes = [vp, vp]
     L.fmnmf_get_state.argtypes = [vp, dp, dp, dp, dp]
     L.fmnmf_set_state.argtypes = [vp, dp, dp, dp, dp]
@@ -172,6 +174,11 @@ class FastMNMF:
         ms = np.zeros(len(KERNELS))
         _check(lib().fmnmf_profile_step(self._ctx, int(n), _dp(ms)))
         return dict(zip(KERNELS, ms.tolist()))
+
+    def init_scm(self):
+        """Replace Q and G~ by the paper's initialisation from the average
+        observed SCM (fmnmf_init_scm)."""
+        _check(lib().fmnmf_init_scm(self._ctx))
 
     def loglik(self) -> float:
         v = ctypes.c_double()
