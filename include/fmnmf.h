@@ -201,8 +201,8 @@ enum fmnmf_kernel {
 /* Instrumented iterations: enqueue n_iter >= 1 iterations without graph
  * capture, with a HIP event pair around every kernel on the context's
  * stream; synchronises and writes the mean duration in milliseconds of each
- * kernel to ms[FMNMF_NUM_KERNELS].  The state advances exactly as with
- * fmnmf_step. */
+ * kernel to ms[FMNMF_NUM_KERNELS] (0 for kernels that are not part of this
+ * context's iteration).  The state advances exactly as with fmnmf_step. */
 int fmnmf_profile_step(fmnmf_ctx* c, int n_iter, double* ms);
 
 /* Short name of kernel k (0 <= k < FMNMF_NUM_KERNELS), or NULL. */
