@@ -55,6 +55,7 @@ def kernel_model(F, T, M, N, K, rb):
 KERNEL_SOURCES = {
     "wpass": "nmf_passes.inc", "hpass": "nmf_passes.inc", "gpass": "nmf_passes.inc",
     "vpass": "spatial.inc", "proj": "spatial.inc", "wiener": "spatial.inc", "ip": "small.inc",
+    "lampass": "nmf_passes.inc",
 }
 COMMON_SOURCES = ["kern_common.h", "kargs.h", "launch.inc", "fmnmf.cpp"]
 
@@ -168,7 +169,8 @@ def fca_leg(torch, fmnmf, synth, X, delta, N, precision, steps, warmup):
     return {"iters_per_s": steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
             "kernels_ms": {k: round(v, 5) for k, v in kms.items() if v > 0},
             "lam_pass": {"bound": "hbm", "algorithmic_bytes": lam_bytes, "achieved": ach, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}}
+                         "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                         "traffic": measured_traffic("lampass", precision + "-fca")}}
 
 
 def cpu_baseline(X, init, delta, seconds):
