@@ -155,6 +155,28 @@ def test_reduced_precision_one_step(device, precision, tol_ll, tol_state, case):
     m.close()
 
 
+@pytest.mark.parametrize("M", [4, 5])
+def test_separate_into_8_byte_aligned_output(device, M):
+    """The filter writes 16-byte vectors only to 16-byte aligned outputs with
+    M == MP; an output that is only 8-byte aligned (allowed by the ABI) gets
+    the same values through element stores."""
+    import torch
+
+    F, T, N, K = 19, 70, 2, 4
+    X, init, delta = synth.random_problem(F, T, M, N, K, seed=77, random_q=True)
+    m = _model(device, X, N, K, init, "fp32", delta)
+    m.step(2)
+    ref = m.separate().cpu().numpy()
+    buf = torch.zeros(N * F * T * M + 1, dtype=torch.complex64, device=device)
+    view = buf[1:].view(N, F, T, M)  # data pointer 8 bytes past a 256-byte boundary
+    assert view.data_ptr() % 16 == 8
+    torch.cuda.synchronize()
+    m.separate(out=view)
+    assert np.array_equal(view.cpu().numpy(), ref)
+    assert buf[0].item() == 0
+    m.close()
+
+
 # Options: the frequency-tied G~ (Eq. 21 summed over f) and the scale
 # normalisation, each against the oracle's step with the same option.
 @pytest.mark.parametrize("tie_g,norm", [(True, False), (False, True), (True, True)])
