@@ -191,6 +191,31 @@ __device__ __forceinline__ void load4(const typename P::R* __restrict__ p, int l
   }
 }
 
+// Sum over the 16 lanes of each DPP row (lanes 16r .. 16r+15), the same bits
+// in all of them: quad_perm [1,0,3,2] and [2,3,0,1] (lane ^ 1, lane ^ 2),
+// row_half_mirror (the other quad of the half row), row_mirror (the other
+// half).  The pairs are those of xor shuffles by 1, 2, 4, 8; IEEE addition
+// is commutative, so both lanes of a pair get the same sum.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <class R>
+__device__ __forceinline__ R row16_sum(R v) {
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
+  return v;
+}
+
 // Orders this wavefront's LDS accesses around a point (stores before it are
 // visible to its loads after it); no other wavefront is involved.
 __device__ __forceinline__ void wave_sync() {
