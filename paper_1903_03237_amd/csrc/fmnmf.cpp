@@ -52,7 +52,6 @@ struct Layout {
   int Sw, Sh, Sg, Sv, tw, fh, tg, tv, nll;
   size_t rb;  // bytes of one real element (FP64: 8, else 4)
   size_t off_kdev;
-  size_t off_Qi64;
   size_t off_Lam;
   size_t off_Xt, off_W, off_H, off_G, off_Wb, off_Wtb, off_Hb, off_Htb, off_Q, off_Qr, off_Qinv, off_logdet,
       off_pw, off_ph, off_pg, off_pv, off_pll, off_status, off_ll, off_Yd, total;
@@ -140,7 +139,6 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   L->off_Qr = take(d->precision == FMNMF_FP64 ? 0 : FP * MP * MP * cb);
   L->off_Qinv = take(FP * MP * MP * cb);
   L->off_logdet = take(FP * 8);
-  L->off_Qi64 = take(FP * MP * MP * 16);
   L->off_pw = take((size_t)L->Sw * 2 * N * KP * FP * rb);
   L->off_ph = take((size_t)L->Sh * 2 * N * KP * TP * rb);
   L->off_pg = take((size_t)L->Sg * 2 * N * FP * MP * rb);
@@ -478,7 +476,7 @@ int fmnmf_step_batch(fmnmf_ctx* const* cs, int count, int n_iter) {
         g_batch.push_back(b);
         ge = b.ge;
       } else if (g) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
       }
       (void)hipGetLastError();
     }
@@ -568,7 +566,6 @@ int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws
   a.Qr = d->precision == FMNMF_FP64 ? static_cast<void*>(a.Q) : static_cast<void*>(ws + L.off_Qr);
   a.Qinv = ws + L.off_Qinv;
   a.logdet = reinterpret_cast<double*>(ws + L.off_logdet);
-  a.Qi64 = reinterpret_cast<double2*>(ws + L.off_Qi64);
   a.pw = ws + L.off_pw;
   a.ph = ws + L.off_ph;
   a.pg = ws + L.off_pg;
@@ -620,11 +617,11 @@ int fmnmf_step(fmnmf_ctx* c, int n_iter) {
         if (rc == FMNMF_OK && e == hipSuccess && g) {
           if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) == hipSuccess) c->graph = g;
           else {
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             c->gexec = nullptr;
           }
         } else if (g) {
-          hipGraphDestroy(g);
+          (void)hipGraphDestroy(g);
         }
         (void)hipGetLastError();
       }

@@ -40,7 +40,6 @@ struct KArgs {
   void* Qr;
   void* Qinv;
   double* logdet;  // [FP] log|det Q_f|^2
-  double2* Qi64;   // [FP][MP][MP] Q_f^-1 (FP64), kept current with Q
   void* pw;        // [Sw][2][N][KP][FP]
   void* ph;        // [Sh][2][N][KP][TP]
   void* pg;        // [Sg][2][N][FP][MP]
@@ -51,7 +50,7 @@ struct KArgs {
   double* ll;
   void* Yd;  // optional [F][T][MP] y~ (derived output for error reports)
   int Sw, Sh, Sg, Sv;  // number of splits of each reduction
-  int tw, fh, tg, tv;  // frames (or bins) covered by one split; multiples of 16 (tv: of 64)
+  int tw, fh, tg, tv;  // frames (or bins) covered by one split; multiples of 16
 };
 
 }  // namespace fmnmf

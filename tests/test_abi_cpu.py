@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1903_03237_amd import fmnmf
@@ -82,3 +83,30 @@ def test_fca_dims_validation_without_gpu(L):
         assert fmnmf.workspace_bytes(fmnmf.make_dims(F, T, M, N, K, prec, flags=flags)) == 0
         assert msg in L.fmnmf_last_error().decode()
     assert fmnmf.workspace_bytes(fmnmf.make_dims(F, T, M, N, 0, "fp64", flags=fmnmf.FCA | fmnmf.TIE_G_OVER_F)) > 0
+
+
+def test_undersized_workspace_is_rejected_without_gpu(L):
+    """fmnmf_init checks the lent workspace against fmnmf_workspace_bytes()
+    before any device work: one byte short gives FMNMF_E_WORKSPACE (the
+    pointers are never dereferenced on that path), and misaligned pointers
+    give FMNMF_E_INVAL."""
+    F, T, M, N, K = 33, 40, 4, 2, 8
+    d = fmnmf.make_dims(F, T, M, N, K, "fp32", 1e-6)
+    need = fmnmf.workspace_bytes(d)
+    assert need > 0
+    W0 = fmnmf._f64c(np.ones((N, K, F)))
+    H0 = fmnmf._f64c(np.ones((N, K, T)))
+    G0 = fmnmf._f64c(np.ones((N, F, M)))
+    Q0 = fmnmf._q_as_f64(np.broadcast_to(np.eye(M, dtype=np.complex128), (F, M, M)).copy())
+    ctx = ctypes.c_void_p(123)
+    fake_x, fake_ws = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21)  # aligned, never touched
+    args = [fmnmf._dp(W0), fmnmf._dp(H0), fmnmf._dp(G0), fmnmf._dp(Q0), None]
+    rc = L.fmnmf_init(ctypes.byref(ctx), ctypes.byref(d), fake_x, fake_ws, need - 1, *args)
+    assert rc == fmnmf.E_WORKSPACE
+    assert ctx.value is None
+    msg = L.fmnmf_last_error().decode()
+    assert str(need) in msg and str(need - 1) in msg
+    rc = L.fmnmf_init(ctypes.byref(ctx), ctypes.byref(d), fake_x, ctypes.c_void_p((1 << 21) + 128), need, *args)
+    assert rc == fmnmf.E_INVAL and "256-byte" in L.fmnmf_last_error().decode()
+    rc = L.fmnmf_init(ctypes.byref(ctx), ctypes.byref(d), ctypes.c_void_p((1 << 20) + 8), fake_ws, need, *args)
+    assert rc == fmnmf.E_INVAL and "16-byte" in L.fmnmf_last_error().decode()

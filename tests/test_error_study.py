@@ -17,6 +17,7 @@ iterations.  Set FMNMF_ERROR_STUDY_FULL=1 to run the same study at M=8, N=5,
 K=32, F=513, T=3000 (minutes of oracle time); it prints one JSON line per path.
 """
 
+import dataclasses
 import json
 import os
 
@@ -100,6 +101,24 @@ def test_reduced_precision_error_over_100_iterations(device):
     init = synth.make_init(F, T, M, N, K, seed=20240602)
     delta = synth.delta_for(X, 1e-8)
     res = _study(device, X, init, delta, N, K, 100, ["fp32", "bf16"])
+    _check(res, monotone_slack=1e-6)
+
+
+def test_reduced_precision_error_mixed_workload_structure(device):
+    """The mixed-precision workload's structure (M=8, N=6, K=64, no noise,
+    delta = 1e-8 mean|x|^2) over its 200 iterations, at F=129 and T=512: this
+    runs the N <= 6 and K <= 64 kernel instantiations of the FP32 and mixed
+    paths for as many iterations as that workload asks for.
+
+    T is not cut further because this noise-free model degenerates when the
+    frames are few for K=64 bases: in the FP64 oracle's own trajectory some
+    V_fm reaches a condition number above 1e7 (beyond FP32) after about 60
+    iterations at T=64, 100 at T=128 and 170 at T=256, while at T=512 it stays
+    below 30 over 200 iterations.  F is cut to keep the oracle's 200
+    iterations within a minute."""
+    c = dataclasses.replace(synth.CONFIGS[4], F=129)
+    X, init, delta = synth.workload(c, T=512)
+    res = _study(device, X, init, delta, c.N, c.K, c.iters, ["fp32", "bf16"])
     _check(res, monotone_slack=1e-6)
 
 

@@ -12,12 +12,9 @@ import pytest
 
 from oracle import fastfca as fca
 from paper_1903_03237_amd import synth
+from parity_util import FP64, assert_close, rel_norm as _rel
 
 pytestmark = pytest.mark.gpu
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def _abi_lam(lam_ftn):  # oracle [F, T, N] -> ABI [N, F, T]
@@ -66,13 +63,13 @@ def test_fca_fp64_one_step_parity(device, case):
 
     l0 = fca.loglik(X, s0, delta)
     assert abs(m.loglik() - l0) <= 1e-10 * abs(l0)
-    assert _rel(m.derived(0), fm.project(X, s0.Q)) < 1e-12
-    assert _rel(m.derived(1), fm.model(s0.lam, s0.G, delta)) < 1e-12
+    assert_close("x~0", m.derived(0), fm.project(X, s0.Q), rtol=1e-12, atol_rel=1e-14)
+    assert_close("y~0", m.derived(1), fm.model(s0.lam, s0.G, delta), rtol=1e-12, atol_rel=1e-14)
     m.step(1)
     s1 = fca.step(X, s0, delta, tie_g=tie)
     lam, G, Q = m.get_state()
     for name, a, b in (("lam", lam, _abi_lam(s1.lam)), ("G", G, s1.G), ("Q", Q, s1.Q)):
-        assert _rel(a, b) < 1e-10, (name, _rel(a, b))
+        assert_close(name, a, b, **FP64)
     l1 = fca.loglik(X, s1, delta)
     assert abs(m.loglik() - l1) <= 1e-10 * abs(l1)
     # inject a later oracle state and step once more
@@ -84,9 +81,9 @@ def test_fca_fp64_one_step_parity(device, case):
     s4 = fca.step(X, s3, delta, tie_g=tie)
     lam, G, Q = m.get_state()
     for name, a, b in (("lam", lam, _abi_lam(s4.lam)), ("G", G, s4.G), ("Q", Q, s4.Q)):
-        assert _rel(a, b) < 1e-10, (name, _rel(a, b))
+        assert_close(name, a, b, **FP64)
     Y = m.separate().cpu().numpy()
-    assert _rel(Y, fca.separate(X, s4, delta)) < 1e-10
+    assert_close("separated", Y, fca.separate(X, s4, delta), **FP64)
     m.close()
 
 
@@ -102,7 +99,8 @@ def test_fca_fp64_trajectory(device):
     np.testing.assert_allclose(lls, ref, rtol=1e-9)
     assert np.all(np.diff(lls) >= -1e-10 * abs(lls[-1]))
     lam, G, Q = m.get_state()
-    assert _rel(lam, _abi_lam(s.lam)) < 1e-8 and _rel(Q, s.Q) < 1e-8
+    for name, a, b in (("lam", lam, _abi_lam(s.lam)), ("G", G, s.G), ("Q", Q, s.Q)):
+        assert_close(name, a, b, rtol=1e-9, atol_rel=1e-12)
     m.close()
 
 

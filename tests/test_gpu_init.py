@@ -13,12 +13,9 @@ import pytest
 from oracle import fastfca as fca
 from oracle import fastmnmf as fm
 from paper_1903_03237_amd import synth
+from parity_util import FP64, assert_close, rel_norm as _rel
 
 pytestmark = pytest.mark.gpu
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def _align_rows(Qg, Qo):
@@ -49,15 +46,17 @@ def test_init_scm_fp64_parity(device, M):
     assert abs(m.loglik() - l0) <= 1e-10 * abs(l0)
     W, H, G, Q = m.get_state()
     assert np.array_equal(W, W0) and np.array_equal(H, H0)
-    assert _rel(G, Go) < 1e-12
-    assert _rel(_align_rows(Q, Qo), Qo) < 1e-10
-    assert _rel(m.derived(0), fm.project(X, Qo)) < 1e-10
+    # eigenvalues to 1e-12, eigenvectors (each row up to its unit factor) to
+    # 1e-10 of the entry plus 1e-12 of the largest
+    assert_close("G", G, Go, rtol=1e-12, atol_rel=1e-14)
+    assert_close("Q", _align_rows(Q, Qo), Qo, rtol=1e-10, atol_rel=1e-12)
+    assert_close("x~", m.derived(0), fm.project(X, Qo), rtol=1e-10, atol_rel=1e-12)
     m.step(1)
     s1 = fm.step(X, s0, delta)
     W, H, G, Q = m.get_state()
     for name, a, b in (("W", W, s1.W), ("H", H, s1.H), ("G", G, s1.G)):
-        assert _rel(a, b) < 1e-10, (name, _rel(a, b))
-    assert _rel(_align_rows(Q, s1.Q), s1.Q) < 1e-10
+        assert_close(name, a, b, **FP64)
+    assert_close("Q1", _align_rows(Q, s1.Q), s1.Q, rtol=1e-10, atol_rel=1e-12)
     l1 = fm.loglik(X, s1, delta)
     assert abs(m.loglik() - l1) <= 1e-10 * abs(l1)
     m.close()
@@ -91,7 +90,8 @@ def test_init_scm_fastfca(device):
     m.step(1)
     s1 = fca.step(X, s0, delta)
     lam, G, Q = m.get_state()
-    assert _rel(lam, np.moveaxis(s1.lam, 2, 0)) < 1e-10 and _rel(G, s1.G) < 1e-10
+    assert_close("lam", lam, np.moveaxis(s1.lam, 2, 0), **FP64)
+    assert_close("G", G, s1.G, **FP64)
     assert abs(m.loglik() - fca.loglik(X, s1, delta)) <= 1e-10 * abs(fca.loglik(X, s1, delta))
     m.close()
 
