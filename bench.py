@@ -39,16 +39,64 @@ def kernel_model(F, T, M, N, K, rb):
     """Algorithmic bytes and flops per launch of each iteration kernel.
 
     Bytes are what the method must move (x~ or X in, x~ out), not partial sums
-    or re-reads; flops count the arithmetic the kernel's formulas need."""
+    or re-reads; flops count the arithmetic the kernel's formulas need;
+    mfma_flops the part of it that is the NMF contractions (lambda = W H and,
+    in the W and H passes, the numerator / denominator sums of Eqs. 23-24)."""
     FT = F * T
     cb = 2 * rb
     return {
-        "wpass": {"bytes": FT * M * rb, "flops": FT * (6 * N * K + 6 * N * M), "bound": "hbm"},
-        "hpass": {"bytes": FT * M * rb, "flops": FT * (6 * N * K + 6 * N * M), "bound": "hbm"},
-        "gpass": {"bytes": FT * M * rb, "flops": FT * (2 * N * K + 6 * N * M), "bound": "hbm"},
+        "wpass": {"bytes": FT * M * rb, "flops": FT * (6 * N * K + 6 * N * M), "mfma_flops": FT * 6 * N * K,
+                  "bound": "hbm"},
+        "hpass": {"bytes": FT * M * rb, "flops": FT * (6 * N * K + 6 * N * M), "mfma_flops": FT * 6 * N * K,
+                  "bound": "hbm"},
+        "gpass": {"bytes": FT * M * rb, "flops": FT * (2 * N * K + 6 * N * M), "mfma_flops": FT * 2 * N * K,
+                  "bound": "hbm"},
         "vpass": {"bytes": FT * M * cb, "flops": FT * (M * M * (4 + 2 * M) + 2 * N * K), "bound": "hbm"},
         "proj": {"bytes": FT * M * (cb + rb), "flops": FT * (8 * M * M + 2 * N * K + 5 * M), "bound": "hbm"},
     }
+
+
+def iteration_bytes(F, T, M, rb):
+    """Algorithmic HBM bytes of one iteration: x~ read by the W, H and G~
+    passes and written by the projection, X read by the V pass and the
+    projection: F T M (4 b_r + 2 b_c)."""
+    return F * T * M * (4 * rb + 2 * 2 * rb)
+
+
+def wiener_bytes(F, T, M, N, rb):
+    """The filter reads X and writes N images: F T M b_c (1 + N)."""
+    return F * T * M * 2 * rb * (1 + N)
+
+
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+
+
+def roofline_table(kms, F, T, M, N, K, precision, wiener_ms=None):
+    """Per-kernel achieved rates from mean launch times (ms): algorithmic
+    GB/s and the fraction of the 8 TB/s HBM peak; for the NMF contractions
+    also the MFMA rate against the dense peak of the path's operand type and
+    the ceiling that the x~ stream (HBM at peak) puts on it."""
+    rb = 8 if precision == "fp64" else 4
+    km = kernel_model(F, T, M, N, K, rb)
+    out = {}
+    for k, d in km.items():
+        if not kms.get(k):
+            continue
+        sec = kms[k] * 1e-3
+        e = {"ms": round(kms[k], 5), "algorithmic_bytes": d["bytes"],
+             "hbm_gbs": d["bytes"] / sec / 1e9, "hbm_frac": d["bytes"] / sec / 1e9 / HBM_PEAK_GBS}
+        if "mfma_flops" in d:
+            peak = MFMA_PEAK_TFLOPS[precision]
+            e["mfma_tflops"] = d["mfma_flops"] / sec / 1e12
+            e["mfma_frac"] = e["mfma_tflops"] / peak
+            # at most this fraction of the MFMA peak while x~ streams at the HBM peak
+            e["mfma_ceiling_frac"] = min(1.0, d["mfma_flops"] / (d["bytes"] / (HBM_PEAK_GBS * 1e9)) / 1e12 / peak)
+        out[k] = e
+    if wiener_ms:
+        b = wiener_bytes(F, T, M, N, rb)
+        out["wiener"] = {"ms": round(wiener_ms, 5), "algorithmic_bytes": b, "hbm_gbs": b / (wiener_ms * 1e-3) / 1e9,
+                         "hbm_frac": b / (wiener_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
 
 # Source files that define each kernel and its launch shape.
@@ -173,6 +221,45 @@ def fca_leg(torch, fmnmf, synth, X, delta, N, precision, steps, warmup):
                          "traffic": measured_traffic("lampass", precision + "-fca")}}
 
 
+def config_leg(torch, fmnmf, synth, cfg_id, precision, steps, warmup):
+    """Another workload of the catalogue on one path: iterations/s with the
+    final Wiener filter in the timed region (as the headline), the filter
+    alone, per-kernel times and their roofline fractions."""
+    c = synth.CONFIGS[cfg_id]
+    X, init, delta = synth.workload(cfg_id)
+    dt = np.complex128 if precision == "fp64" else np.complex64
+    tdt = torch.complex128 if precision == "fp64" else torch.complex64
+    Xd = torch.from_numpy(np.ascontiguousarray(X.astype(dt))).to("cuda:0")
+    del X
+    out = torch.empty((c.N, c.F, c.T, c.M), dtype=tdt, device="cuda:0")
+    m = fmnmf.FastMNMF(Xd, c.N, c.K, init, precision=precision, delta=delta)
+    m.step(warmup)
+    m.loglik()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.step(steps)
+    m.separate(out=out)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    m.separate(out=out)
+    torch.cuda.synchronize()
+    wiener_ms = (time.perf_counter() - t1) * 1e3
+    kms = m.profile(5)
+    m.close()
+    del Xd, out
+    torch.cuda.empty_cache()
+    iters = steps / elapsed
+    rb = 8 if precision == "fp64" else 4
+    it_ms = (elapsed * 1e3 - wiener_ms) / steps  # the steps' share of the timed run
+    return {"workload": f"{c.name}: M={c.M} N={c.N} K={c.K} F={c.F} T={c.T}", "precision": precision,
+            "steps": steps, "iters_per_s": iters, "ms_per_step": elapsed * 1e3 / steps,
+            "tf_bins_per_s": iters * c.F * c.T, "wiener_ms": wiener_ms,
+            "kernels_ms": {k: round(v, 5) for k, v in kms.items() if v},
+            "iteration_hbm_frac": iteration_bytes(c.F, c.T, c.M, rb) / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernels_roofline": roofline_table(kms, c.F, c.T, c.M, c.N, c.K, precision, wiener_ms)}
+
+
 def cpu_baseline(X, init, delta, seconds):
     from oracle import fastmnmf as fm
 
@@ -258,6 +345,9 @@ def main():
                     help="requests of the serving leg (0 disables it)")
     ap.add_argument("--fca-paths", default="fp32,fp64",
                     help="precision paths of the FastFCA leg on the same mixture (empty disables it)")
+    ap.add_argument("--legs", default="2:fp64,4:bf16",
+                    help="other workloads of the catalogue to time, as config:path pairs (empty disables)")
+    ap.add_argument("--leg-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -291,6 +381,13 @@ def main():
     for p in [q.strip() for q in args.fca_paths.split(",") if q.strip()]:
         print(f"[bench] FastFCA {p}: {args.warmup} warmup + {args.steps} steps", file=sys.stderr, flush=True)
         fca[p] = fca_leg(torch, fmnmf, synth, X, delta, N, p, args.steps, args.warmup)
+
+    legs = {}
+    for item in [q.strip() for q in args.legs.split(",") if q.strip()]:
+        cid, prec = item.split(":")
+        print(f"[bench] workload {cid} on {prec}: {args.warmup} warmup + {args.leg_steps} steps", file=sys.stderr,
+              flush=True)
+        legs[item] = config_leg(torch, fmnmf, synth, int(cid), prec, args.leg_steps, args.warmup)
 
     serving = None
     if args.serving_requests > 0:
@@ -343,6 +440,11 @@ def main():
         "kernels_ms": {k: round(v, 5) for k, v in kms.items()},
         "wiener_ms": h["wiener_ms"],
         "roofline": roof,
+        "kernels_roofline": roofline_table(kms, F, T, M, N, K, head, h["wiener_ms"]),
+        # one iteration's algorithmic bytes over its time in the timed run (the
+        # steps' share: elapsed minus one Wiener filter)
+        "iteration_hbm_frac": iteration_bytes(F, T, M, rb) * args.steps
+        / (h["elapsed"] - h["wiener_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
     for p, r in res.items():
         e = {"iters_per_s": args.steps / r["elapsed"], "ms_per_step": r["elapsed"] * 1e3 / args.steps,
@@ -352,6 +454,8 @@ def main():
             ref = base["ll_step1"]
             e["ll_rel_err_step1"] = abs(r["ll_step1"] - ref) / max(abs(ref), F * T * M)
         out["paths"][p] = e
+    if legs:
+        out["other_workloads"] = legs
     if fca:
         out["fastfca"] = fca
     if serving is not None:

@@ -52,6 +52,7 @@ struct Layout {
   int Sw, Sh, Sg, Sv, tw, fh, tg, tv, nll;
   size_t rb;  // bytes of one real element (FP64: 8, else 4)
   size_t off_kdev;
+  size_t off_Qi64;
   size_t off_Lam;
   size_t off_Xt, off_W, off_H, off_G, off_Wb, off_Wtb, off_Hb, off_Htb, off_Q, off_Qr, off_Qinv, off_logdet,
       off_pw, off_ph, off_pg, off_pv, off_pll, off_status, off_ll, off_Yd, total;
@@ -104,7 +105,7 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   // T=3000 on MI355X: the best split counts lie near these totals; the G~
   // pass stays below 512 because its FP32 form holds only two per CU).
   // FMNMF_WG_TARGET overrides the W / H / G~ targets.
-  int tw = 660, th = 752, tg = 480;
+  int tw = 660, th = 752, tg = 480, tv = 512;
   if (const char* e = std::getenv("FMNMF_WG_TARGET")) tw = th = tg = std::max(1, std::atoi(e));
   // FMNMF_SPLITS="w,h,g,v" fixes the number of splits per pass (0 = automatic)
   int fix[4] = {0, 0, 0, 0};
@@ -113,7 +114,7 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   choose_split(nF, d->T, slots_for(0, nF, tw), 64, 16, &L->Sw, &L->tw);
   choose_split(nT, d->F, slots_for(1, nT, th), 64, 16, &L->Sh, &L->fh);
   choose_split(nF, d->T, slots_for(2, nF, tg), 64, 16, &L->Sg, &L->tg);
-  choose_split(nF, d->T, slots_for(3, nF, 16 * nF), 32, 64, &L->Sv, &L->tv);
+  choose_split(nF, d->T, slots_for(3, nF, tv), 32, 16, &L->Sv, &L->tv);
   L->nll = cdiv(d->F, 16) * cdiv(d->T, 64);
   L->rb = d->precision == FMNMF_FP64 ? 8 : 4;
   const size_t rb = L->rb, cb = 2 * rb;
@@ -139,6 +140,7 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   L->off_Qr = take(d->precision == FMNMF_FP64 ? 0 : FP * MP * MP * cb);
   L->off_Qinv = take(FP * MP * MP * cb);
   L->off_logdet = take(FP * 8);
+  L->off_Qi64 = take(FP * MP * MP * 16);
   L->off_pw = take((size_t)L->Sw * 2 * N * KP * FP * rb);
   L->off_ph = take((size_t)L->Sh * 2 * N * KP * TP * rb);
   L->off_pg = take((size_t)L->Sg * 2 * N * FP * MP * rb);
@@ -566,6 +568,7 @@ int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws
   a.Qr = d->precision == FMNMF_FP64 ? static_cast<void*>(a.Q) : static_cast<void*>(ws + L.off_Qr);
   a.Qinv = ws + L.off_Qinv;
   a.logdet = reinterpret_cast<double*>(ws + L.off_logdet);
+  a.Qi64 = reinterpret_cast<double2*>(ws + L.off_Qi64);
   a.pw = ws + L.off_pw;
   a.ph = ws + L.off_ph;
   a.pg = ws + L.off_pg;

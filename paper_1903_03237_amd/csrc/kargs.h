@@ -40,6 +40,7 @@ struct KArgs {
   void* Qr;
   void* Qinv;
   double* logdet;  // [FP] log|det Q_f|^2
+  double2* Qi64;   // [FP][MP][MP] Q_f^-1 (FP64), recomputed from Q_f after every update
   void* pw;        // [Sw][2][N][KP][FP]
   void* ph;        // [Sh][2][N][KP][TP]
   void* pg;        // [Sg][2][N][FP][MP]

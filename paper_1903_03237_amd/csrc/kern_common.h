@@ -8,6 +8,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kargs.h"
 
 namespace fmnmf {
@@ -133,62 +135,98 @@ __device__ __forceinline__ float rcp<float>(float x) {
 }
 
 // ---------------------------------------------------------------------------
-// PSD tile engine, Eq. (9): lambda_ftn = sum_k w_nkf h_nkt for a 16 x 16 tile.
-//
-// TF = true : rows are frames, columns frequencies.  Lane l gets
-//             lambda(f = f0 + (l & 15), t = t0 + row(l, v)).
-// TF = false: rows are frequencies, columns frames.  Lane l gets
+// PSD tile engine, Eq. (9): lambda_ftn = sum_k w_nkf h_nkt for a 16 x 16 tile
+// of frequencies x frames, one MFMA chain over the bases (K = 16 KT, padded
+// rows are zero).  The operand that moves along the workgroup's reduction
+// axis is loaded into registers an iteration ahead (HOp); the fixed one is
+// read from LDS (or global memory).  Output layouts:
+//   TF = true (rows frames, columns frequencies): lane l gets
+//             lambda(f = f0 + (l & 15), t = t0 + row(l, v));
+//   TF = false (rows frequencies, columns frames): lane l gets
 //             lambda(f = f0 + row(l, v), t = t0 + (l & 15)).
-// Operands (either may live in LDS or global memory):
-//   FP32/FP64: hk(k) points at h_n,k,t0 (stride hs between k), wk likewise
-//              for w_n,k,f0 (stride ws); column c = l & 15 is added here.
-//   bf16:      ht points at h_n,t0,0 of the [t][KPB] copy (row stride hs),
-//              wt at w_n,f0,0 of the [f][KPB] copy (row stride ws).
-// The loop over k is fully unrolled (KP = 16 * KT rows, padded rows are
-// zero) so that all operand loads are issued before the MFMA chain.
 // ---------------------------------------------------------------------------
-template <class P, bool TF, int KT, class RH, class RW>
-__device__ __forceinline__ typename P::Acc4 lam_tile(const RH* __restrict__ hk, int hs, const RW* __restrict__ wk,
-                                                     int ws, int l) {
+// The moving operand of a lambda tile, loaded ahead of its use: source n's
+// values for the 16 columns from x0 of an [N][KP][L] array (FP32 / FP64: rows
+// k = 4 i + g of column x0 + c) or of its [N][L][KPB] bf16 copy (the 8 k
+// values [32 i + 8 g, +8) of row x0 + c).  KT = 0 (unconstrained source
+// model): the lane's four lambda values themselves, read from Lam.
+template <class P, int KT>
+struct HOp {
+  static constexpr int NK = KT == 0 ? 4 : P::BF ? (16 * KT + 31) / 32 : 4 * KT;
+  using E = typename std::conditional<P::BF && KT != 0, bf16x8, typename P::R>::type;
+  E h[NK];
+};
+template <class P, int KT>
+__device__ __forceinline__ void mop_load(HOp<P, KT>& o, const KArgs& a, const void* arr, const __bf16* arrb, int L,
+                                         int n, int x0, int l) {
+  using R = typename P::R;
+  const int c = l & 15, g = l >> 4;
+  if constexpr (KT == 0) {
+    (void)o; (void)a; (void)arr; (void)arrb; (void)L; (void)n; (void)x0; (void)c; (void)g;
+  } else if constexpr (P::BF) {
+    const __bf16* hk = arrb + ((size_t)n * L + x0 + c) * a.KPB + 8 * g;
+#pragma unroll
+    for (int i = 0; i < HOp<P, KT>::NK; ++i) o.h[i] = *reinterpret_cast<const bf16x8*>(hk + 32 * i);
+  } else {
+    const R* hk = static_cast<const R*>(arr) + (size_t)n * a.KP * L + x0 + c;
+#pragma unroll
+    for (int i = 0; i < HOp<P, KT>::NK; ++i) o.h[i] = hk[(size_t)(4 * i + g) * L];
+  }
+}
+// KT = 0: the lambda values of the tile (f0, t0) of Lam [N][FP][TP] in the
+// lane layout of the tile (TF: f = f0 + c, t = t0 + row; else f = f0 + row,
+// t = t0 + c).
+template <class P, bool TF, int KT>
+__device__ __forceinline__ void lamv_load(HOp<P, KT>& o, const KArgs& a, int n, int f0, int t0, int l) {
+  using R = typename P::R;
+  const R* L = static_cast<const R*>(a.Lam) + (size_t)n * a.FP * a.TP;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = P::row(l, v), col = l & 15;
+    const int f = TF ? f0 + col : f0 + row, t = TF ? t0 + row : t0 + col;
+    o.h[v] = L[(size_t)f * a.TP + t];
+  }
+}
+// V pass form: the H operand of the frame tile from t0 (TF layout).
+template <class P, int KT>
+__device__ __forceinline__ void hop_load(HOp<P, KT>& o, const KArgs& a, int n, int f0, int t0, int l) {
+  if constexpr (KT == 0) lamv_load<P, true, KT>(o, a, n, f0, t0, l);
+  else mop_load<P, KT>(o, a, a.H, a.Htb, a.TP, n, t0, l);
+}
+// lambda tile from a loaded moving operand m and the fixed operand fk (FP32 /
+// FP64: rows of stride fs, element (4 i + g, c); bf16: rows c of stride fs,
+// elements [32 i + 8 g, +8)), in LDS or global memory.  MOV_A: the moving
+// operand is the MFMA's A (rows of the tile), else its B (columns).
+template <class P, int KT, bool MOV_A, class RW>
+__device__ __forceinline__ typename P::Acc4 lam_mov(const HOp<P, KT>& m, const RW* __restrict__ fk, int fs, int l) {
   using Acc4 = typename P::Acc4;
   Acc4 acc = zero4<Acc4>();
-  const int c = l & 15, g = l >> 4;
-  if constexpr (!P::BF) {
-    using R = typename P::R;
-    constexpr int NK = 4 * KT;  // 16*KT rows / depth 4
-    R h[NK], w[NK];
+  if constexpr (KT == 0) {
+    (void)fk; (void)fs; (void)l;
 #pragma unroll
-    for (int i = 0; i < NK; ++i) {
-      h[i] = hk[(4 * i + g) * hs + c];
-      w[i] = wk[(4 * i + g) * ws + c];
-    }
-#pragma unroll
-    for (int i = 0; i < NK; ++i) acc = TF ? P::mma(h[i], w[i], acc) : P::mma(w[i], h[i], acc);
+    for (int v = 0; v < 4; ++v) acc[v] = m.h[v];
   } else {
-    constexpr int NK = (16 * KT + 31) / 32;
-    bf16x8 h[NK], w[NK];
+    const int c = l & 15, g = l >> 4;
+    if constexpr (P::BF) {
+      bf16x8 f[HOp<P, KT>::NK];
 #pragma unroll
-    for (int i = 0; i < NK; ++i) {
-      h[i] = *reinterpret_cast<const bf16x8*>(hk + c * hs + 32 * i + 8 * g);
-      w[i] = *reinterpret_cast<const bf16x8*>(wk + c * ws + 32 * i + 8 * g);
+      for (int i = 0; i < HOp<P, KT>::NK; ++i) f[i] = *reinterpret_cast<const bf16x8*>(fk + c * fs + 32 * i + 8 * g);
+#pragma unroll
+      for (int i = 0; i < HOp<P, KT>::NK; ++i) acc = MOV_A ? P::mma(m.h[i], f[i], acc) : P::mma(f[i], m.h[i], acc);
+    } else {
+      typename P::R f[HOp<P, KT>::NK];
+#pragma unroll
+      for (int i = 0; i < HOp<P, KT>::NK; ++i) f[i] = fk[(4 * i + g) * fs + c];
+#pragma unroll
+      for (int i = 0; i < HOp<P, KT>::NK; ++i) acc = MOV_A ? P::mma(m.h[i], f[i], acc) : P::mma(f[i], m.h[i], acc);
     }
-#pragma unroll
-    for (int i = 0; i < NK; ++i) acc = TF ? P::mma(h[i], w[i], acc) : P::mma(w[i], h[i], acc);
   }
   return acc;
 }
-
-// Per-lane four values at p[row(l, 0..3)] of a contiguous 16-run: one vector
-// load for the FP32 layout (rows 4g..4g+3), four scalar loads for FP64.
-template <class P>
-__device__ __forceinline__ void load4(const typename P::R* __restrict__ p, int l, typename P::R (&o)[4]) {
-  if constexpr (sizeof(typename P::R) == 4) {
-    const f32x4 v = *reinterpret_cast<const f32x4*>(p + 4 * (l >> 4));
-    o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
-  } else {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) o[r] = p[P::row(l, r)];
-  }
+// V pass form: TF layout, H moving (rows = frames), W fixed (columns).
+template <class P, int KT, class RW>
+__device__ __forceinline__ typename P::Acc4 lam_hop(const HOp<P, KT>& o, const RW* __restrict__ wk, int ws, int l) {
+  return lam_mov<P, KT, true>(o, wk, ws, l);
 }
 
 // Sum over the 16 lanes of each DPP row (lanes 16r .. 16r+15), the same bits

@@ -11,7 +11,10 @@ Requests (mixtures of different M, N, K and T) arrive over time.  The server
   class, from a HIP graph captured per composition;
 * lets requests that arrive while others run join at the next chunk
   boundary, and separates finished requests (Wiener filter) on their own
-  streams while the next chunk of the others runs.
+  streams while the next chunk of the others runs;
+* retires a request whose context latched a numerical fault (a singular IP
+  system, a non-finite likelihood) with that error code, while the others
+  continue: every context's arithmetic and status word are its own.
 
 `run_sequential` serves the same requests one at a time with fmnmf_step, the
 baseline the batched server is compared with.
@@ -47,6 +50,8 @@ class Result:
     finished: float
     loglik: float
     Y: object = None  # separated images [N, F, T, M] (device tensor) when kept
+    error: int = 0    # 0, or the FMNMF_E_* code the request was retired with
+    message: str = ""
 
     @property
     def latency(self) -> float:
@@ -148,13 +153,38 @@ class Server:
                 planned[s.req.rid] = 0
                 used += fp
                 pi += 1
+                if s.req.iters == 0:  # nothing to iterate: the filter of its initial state
+                    retire(s)
+
+        def retire(s, err=None):
+            """Separate a finished request (or record its error) and free its slot."""
+            nonlocal used
+            active.remove(s)
+            code, msg, ll = 0, "", float("nan")
+            try:
+                if err is not None:
+                    raise err
+                s.model.separate(out=s.out)  # on its own stream
+                ll = s.model.loglik()
+            except fmnmf.FmnmfError as e:  # a numerical fault of this request only
+                code, msg = e.code, str(e)
+            results.append(Result(s.req.rid, s.req.arrival, s.admitted, clock(), ll,
+                                  s.out if (self.keep and code == 0) else None, code, msg))
+            used -= footprint(s.req, self.precision)
+            planned.pop(s.req.rid, None)
+            s.model.close()
 
         def enqueue():
             comp = [s for s in active if planned[s.req.rid] < s.req.iters]
             if not comp:
                 return False
             n = min(self.chunk, min(s.req.iters - planned[s.req.rid] for s in comp))
-            fmnmf.step_batch([s.model for s in comp], n)
+            try:
+                fmnmf.step_batch([s.model for s in comp], n)
+            except fmnmf.FmnmfError as e:  # a launch failed: retire the batch's requests
+                for s in comp:
+                    retire(s, e)
+                return True
             ev = torch.cuda.Event()
             ev.record(comp[0].model.stream)
             for s in comp:
@@ -180,16 +210,9 @@ class Server:
             admit()
             while len(inflight) < 2 and enqueue():
                 pass
-            done = [s for s in comp if s.done >= s.req.iters]
+            done = [s for s in comp if s.done >= s.req.iters and s in active]
             for s in done:
-                active.remove(s)
-                s.model.separate(out=s.out)  # on its own stream
-                ll = s.model.loglik()
-                results.append(Result(s.req.rid, s.req.arrival, s.admitted, clock(), ll,
-                                      s.out if self.keep else None))
-                used -= footprint(s.req, self.precision)
-                del planned[s.req.rid]
-                s.model.close()
+                retire(s)
         return sorted(results, key=lambda r: r.rid)
 
 
@@ -210,10 +233,15 @@ def run_sequential(requests, precision: str = "bf16", device: str = "cuda:0",
         F, T, M = r.X.shape
         out = torch.empty((r.N, F, T, M), dtype=tdt, device=device)
         m = fmnmf.FastMNMF(X, r.N, r.K, r.init, precision=precision, delta=r.delta)
-        m.step(r.iters)
-        m.separate(out=out)
-        ll = m.loglik()
-        results.append(Result(r.rid, r.arrival, adm, time.perf_counter() - t0, ll, out if keep_outputs else None))
+        code, msg, ll = 0, "", float("nan")
+        try:
+            m.step(r.iters)
+            m.separate(out=out)
+            ll = m.loglik()
+        except fmnmf.FmnmfError as e:
+            code, msg = e.code, str(e)
+        results.append(Result(r.rid, r.arrival, adm, time.perf_counter() - t0, ll,
+                              out if (keep_outputs and code == 0) else None, code, msg))
         m.close()
     return sorted(results, key=lambda r: r.rid)
 

@@ -64,3 +64,25 @@ def test_request_over_budget_is_rejected(device):
     reqs = _requests()[:1]
     with pytest.raises(ValueError):
         serve.Server(hbm_budget=1024, device=device).run(reqs)
+
+
+def test_faulting_request_retires_while_others_match_alone(device):
+    """A request whose mixture holds a NaN latches FMNMF_E_NONFINITE in its own
+    context; the server retires it with that code and the other requests,
+    batched with it, still equal the same requests run alone."""
+    from paper_1903_03237_amd import fmnmf, serve
+
+    reqs = _requests()[:5]
+    bad = reqs[2]
+    Xb = bad.X.copy()
+    Xb[3, 7, 1] = complex(np.nan, 0.0)
+    reqs[2] = serve.Request(bad.rid, bad.arrival, Xb, bad.N, bad.K, bad.init, bad.delta, bad.iters)
+    srv = serve.Server(precision="bf16", hbm_budget=1 << 34, max_active=8, chunk=4, device=device,
+                       keep_outputs=True)
+    got = srv.run(reqs)
+    assert got[2].error == fmnmf.E_NONFINITE and got[2].Y is None
+    good = [r for i, r in enumerate(reqs) if i != 2]
+    alone = serve.run_sequential(good, precision="bf16", device=device, keep_outputs=True)
+    for g, a in zip([r for r in got if r.rid != 2], alone):
+        assert g.error == 0 and g.loglik == a.loglik
+        np.testing.assert_array_equal(g.Y.cpu().numpy(), a.Y.cpu().numpy())
