@@ -67,9 +67,11 @@ def test_request_over_budget_is_rejected(device):
 
 
 def test_faulting_request_retires_while_others_match_alone(device):
-    """A request whose mixture holds a NaN latches FMNMF_E_NONFINITE in its own
-    context; the server retires it with that code and the other requests,
-    batched with it, still equal the same requests run alone."""
+    """A request whose mixture holds a NaN latches a numerical fault in its own
+    context (a non-finite likelihood, and from the first IP update on a
+    singular system, which is reported first); the server retires it with
+    that code and the other requests, batched with it, still equal the same
+    requests run alone."""
     from paper_1903_03237_amd import fmnmf, serve
 
     reqs = _requests()[:5]
@@ -80,7 +82,7 @@ def test_faulting_request_retires_while_others_match_alone(device):
     srv = serve.Server(precision="bf16", hbm_budget=1 << 34, max_active=8, chunk=4, device=device,
                        keep_outputs=True)
     got = srv.run(reqs)
-    assert got[2].error == fmnmf.E_NONFINITE and got[2].Y is None
+    assert got[2].error in (fmnmf.E_NONFINITE, fmnmf.E_SINGULAR) and got[2].Y is None
     good = [r for i, r in enumerate(reqs) if i != 2]
     alone = serve.run_sequential(good, precision="bf16", device=device, keep_outputs=True)
     for g, a in zip([r for r in got if r.rid != 2], alone):
