@@ -116,6 +116,25 @@ size_t fmnmf_footprint_bytes(const fmnmf_dims* d);
 int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws_dev, size_t ws_bytes,
                const double* W0, const double* H0, const double* G0, const double* Q0, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): fmnmf_init with
+ * the workspace taken from a static device array of the library,
+ * FMNMF_SCRATCH_BYTES bytes per GPU, held from the library's first use on a
+ * GPU until the process ends, instead of a caller-lent buffer.  Arguments
+ * and results are those of fmnmf_init (X_dev is still caller memory); the
+ * call allocates no device memory.
+ *   - FMNMF_E_WORKSPACE if fmnmf_workspace_bytes(d) exceeds
+ *     FMNMF_SCRATCH_BYTES.
+ *   - One such context per GPU at a time: the array is shared by every call
+ *     on that GPU and keeps the last context's contents (the call clears it).
+ *     While one lives, another fmnmf_init_noalloc on the same GPU (the
+ *     calling thread's current device) returns FMNMF_E_INVAL; fmnmf_destroy
+ *     synchronises the context's stream and releases the array.
+ *   - Such a context cannot be passed to fmnmf_step_batch (FMNMF_E_INVAL). */
+#define FMNMF_SCRATCH_BYTES (256u << 20)
+int fmnmf_init_noalloc(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, const double* W0,
+                       const double* H0, const double* G0, const double* Q0, void* stream);
+
 /* Enqueue n_iter >= 0 full iterations (W, H, G~, Q, x~, L; with FMNMF_FCA
  * lambda, G~, Q, x~, L); asynchronous.
  * Returns only launch errors. */

@@ -23,7 +23,7 @@ ARCH = "gfx950"
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-result"]
-UNITS = ["inst_f64.hip", "inst_f32.hip", "inst_bf16.hip", "fmnmf.cpp"]
+UNITS = ["inst_f64.hip", "inst_f32.hip", "inst_bf16.hip", "scratch.hip", "fmnmf.cpp"]
 
 
 def _compile(src: str) -> str:

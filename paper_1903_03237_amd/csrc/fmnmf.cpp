@@ -20,6 +20,7 @@
 
 #include "kargs.h"
 #include "kernels.h"
+#include "scratch.h"
 
 using fmnmf::KArgs;
 
@@ -183,6 +184,7 @@ struct fmnmf_ctx {
   bool graph_tried = false;
   KArgs* kdev = nullptr;      // device copy of a (read by batched launches)
   hipEvent_t ev = nullptr;    // joins this context's stream with a batch's stream
+  int scratch_dev = -1;       // device whose scratch array is the workspace (fmnmf_init_noalloc)
 };
 
 namespace {
@@ -440,6 +442,8 @@ int fmnmf_step_batch(fmnmf_ctx* const* cs, int count, int n_iter) {
     for (int j = 0; j < i; ++j)
       if (cs[j] == cs[i]) return fail(FMNMF_E_INVAL, "context %d appears twice", i);
   }
+  for (int i = 0; i < count; ++i)
+    if (!cs[i]->ev) return fail(FMNMF_E_INVAL, "context %d was made by fmnmf_init_noalloc (not batched)", i);
   if (n_iter == 0) return FMNMF_OK;
   hipStream_t s0 = cs[0]->s;
   // the batch's stream waits for every context's earlier work ...
@@ -514,8 +518,15 @@ size_t fmnmf_footprint_bytes(const fmnmf_dims* d) {
   return ws + x + (size_t)d->N * x;
 }
 
-int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws_dev, size_t ws_bytes,
-               const double* W0, const double* H0, const double* G0, const double* Q0, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Shared body of fmnmf_init and fmnmf_init_noalloc.  with_event: create the
+// event that joins the context's stream with a batch's (fmnmf_step_batch).
+int init_ctx(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws_dev, size_t ws_bytes,
+             const double* W0, const double* H0, const double* G0, const double* Q0, void* stream,
+             bool with_event, int scratch_dev) {
   if (!out) return fail(FMNMF_E_INVAL, "out is NULL");
   *out = nullptr;
   int rc = check_dims(d);
@@ -587,20 +598,58 @@ int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws
   a.tg = L.tg;
   a.tv = L.tv;
   c->kdev = reinterpret_cast<KArgs*>(ws + L.off_kdev);
+  c->scratch_dev = scratch_dev;
+  // the workspace starts at zero (padding of every array, the status word)
   hipError_t e = hipMemsetAsync(ws_dev, 0, L.total, c->s);
   if (e == hipSuccess) e = hipMemcpyAsync(c->kdev, &c->a, sizeof(KArgs), hipMemcpyHostToDevice, c->s);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
+  if (e == hipSuccess && with_event) e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
   if (e != hipSuccess) {
+    if (c->ev) (void)hipEventDestroy(c->ev);
     delete c;
     return fail(FMNMF_E_HIP, "context set-up: %s", hipGetErrorString(e));
   }
   rc = upload_state(c, W0, H0, G0, Q0);
   if (rc) {
+    if (c->ev) (void)hipEventDestroy(c->ev);
     delete c;
     return rc;
   }
   *out = c;
   return FMNMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fmnmf_init(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws_dev, size_t ws_bytes,
+               const double* W0, const double* H0, const double* G0, const double* Q0, void* stream) {
+  return init_ctx(out, d, X_dev, ws_dev, ws_bytes, W0, H0, G0, Q0, stream, true, -1);
+}
+
+int fmnmf_init_noalloc(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, const double* W0,
+                       const double* H0, const double* G0, const double* Q0, void* stream) {
+  if (!out) return fail(FMNMF_E_INVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_dims(d);
+  if (rc) return rc;
+  Layout L;
+  make_layout(d, &L);
+  if (L.total > (size_t)FMNMF_SCRATCH_BYTES)
+    return fail(FMNMF_E_WORKSPACE, "workspace of %zu bytes exceeds the static scratch of %zu bytes", L.total,
+                (size_t)FMNMF_SCRATCH_BYTES);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  void* ws = nullptr;
+  hipError_t e = hipSuccess;
+  const int sr = fmnmf::scratch_acquire(dev, &ws, &e);
+  if (sr == fmnmf::SCRATCH_HIP_ERROR)
+    return fail(FMNMF_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+  if (sr == fmnmf::SCRATCH_IN_USE)
+    return fail(FMNMF_E_INVAL, "the static scratch of device %d is held by a live context", dev);
+  rc = init_ctx(out, d, X_dev, ws, FMNMF_SCRATCH_BYTES, W0, H0, G0, Q0, stream, false, dev);
+  if (rc) fmnmf::scratch_release(dev);
+  return rc;
 }
 
 int fmnmf_step(fmnmf_ctx* c, int n_iter) {
@@ -750,6 +799,11 @@ void fmnmf_destroy(fmnmf_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->ev) (void)hipEventDestroy(c->ev);
+  if (c->scratch_dev >= 0) {
+    // the scratch may be handed to the next context once this one's work is done
+    (void)hipStreamSynchronize(c->s);
+    fmnmf::scratch_release(c->scratch_dev);
+  }
   delete c;
 }
 

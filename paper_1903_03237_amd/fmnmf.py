@@ -24,7 +24,7 @@ OK, E_INVAL, E_UNSUPPORTED, E_WORKSPACE, E_HIP, E_SINGULAR, E_NONFINITE = 0, -1,
 EXPORTS = ("fmnmf_workspace_bytes", "fmnmf_footprint_bytes", "fmnmf_init", "fmnmf_step",
            "fmnmf_loglik", "fmnmf_separate", "fmnmf_get_state", "fmnmf_set_state",
            "fmnmf_get_derived", "fmnmf_destroy", "fmnmf_last_error", "fmnmf_profile_step",
-           "fmnmf_kernel_name", "fmnmf_step_batch", "fmnmf_init_scm")
+           "fmnmf_kernel_name", "fmnmf_step_batch", "fmnmf_init_scm", "fmnmf_init_noalloc")
 KERNELS = ("wpass", "mu_w", "hpass", "mu_h", "gpass", "mu_g", "vpass", "ip", "norm", "proj", "lam")
 
 
@@ -58,6 +58,8 @@ def lib():
     L.fmnmf_footprint_bytes.argtypes = [ctypes.POINTER(Dims)]
     L.fmnmf_footprint_bytes.restype = sz
     L.fmnmf_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Dims), vp, vp, sz, dp, dp, dp, dp, vp]
+    L.fmnmf_init_noalloc.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Dims), vp, dp, dp, dp, dp, vp]
+    L.fmnmf_init_noalloc.restype = ctypes.c_int
     L.fmnmf_step.argtypes = [vp, ctypes.c_int]
     L.fmnmf_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int]
     L.fmnmf_step_batch.restype = ctypes.c_int
@@ -133,14 +135,16 @@ class FastMNMF:
              lifetime of the object.
     init     (W0 [N,K,F], H0 [N,K,T], G0 [N,F,M], Q0 [F,M,M] complex) host arrays.
     normalize / tie_g  the FMNMF_NORMALIZE / FMNMF_TIE_G_OVER_F options.
+    noalloc  use fmnmf_init_noalloc: the workspace is the library's static
+             device array (one such model per device at a time).
     """
 
     def __init__(self, X, N: int, K: int, init, precision="fp64", delta=0.0,
-                 derived=False, stream=None, normalize=False, tie_g=False):
+                 derived=False, stream=None, normalize=False, tie_g=False, noalloc=False):
         flags = (WITH_DERIVED if derived else 0) | (NORMALIZE if normalize else 0) | (TIE_G_OVER_F if tie_g else 0)
-        self._open(X, N, K, init, precision, delta, flags, stream)
+        self._open(X, N, K, init, precision, delta, flags, stream, noalloc)
 
-    def _open(self, X, N, K, init, precision, delta, flags, stream):
+    def _open(self, X, N, K, init, precision, delta, flags, stream, noalloc=False):
         import torch
 
         F, T, M = X.shape
@@ -155,15 +159,21 @@ class FastMNMF:
         nbytes = workspace_bytes(self.dims)
         if nbytes == 0:
             raise FmnmfError(E_INVAL, lib().fmnmf_last_error().decode())
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+        self.ws = None if noalloc else torch.empty(nbytes, dtype=torch.uint8, device=X.device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=X.device)
         torch.cuda.current_stream(X.device).synchronize()  # X / ws are ready before our stream uses them
         W0, H0, G0, Q0 = init
         self._ctx = ctypes.c_void_p()
-        _check(lib().fmnmf_init(ctypes.byref(self._ctx), ctypes.byref(self.dims),
-                                ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
-                                nbytes, _dp(_f64c(W0)), _dp(None if H0 is None else _f64c(H0)), _dp(_f64c(G0)),
-                                _dp(_q_as_f64(Q0)), ctypes.c_void_p(self.stream.cuda_stream)))
+        args = (_dp(_f64c(W0)), _dp(None if H0 is None else _f64c(H0)), _dp(_f64c(G0)), _dp(_q_as_f64(Q0)),
+                ctypes.c_void_p(self.stream.cuda_stream))
+        if noalloc:
+            with torch.cuda.device(X.device):
+                _check(lib().fmnmf_init_noalloc(ctypes.byref(self._ctx), ctypes.byref(self.dims),
+                                                ctypes.c_void_p(X.data_ptr()), *args))
+        else:
+            _check(lib().fmnmf_init(ctypes.byref(self._ctx), ctypes.byref(self.dims),
+                                    ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                                    nbytes, *args))
 
     # -- iteration ---------------------------------------------------------
     def step(self, n: int = 1):

@@ -1,9 +1,11 @@
-// Host-only stand-ins for the kernel launchers of libfmnmf.so, for building
+// Host-only stand-ins for the kernel launchers (and the static scratch
+// lookup) of libfmnmf.so, for building
 // the C ABI's host code (fmnmf.cpp) with the address and undefined-behaviour
 // sanitizers on a machine without a GPU.  Every launcher reports failure;
 // the checks that use this build exercise only paths that return before any
 // device work.
 #include "../../paper_1903_03237_amd/csrc/kernels.h"
+#include "../../paper_1903_03237_amd/csrc/scratch.h"
 
 namespace fmnmf {
 
@@ -31,5 +33,11 @@ FM_STUB(bf16)
 #undef FM_STUB
 
 hipError_t launch_ll_final(const KArgs&, hipStream_t) { return hipErrorNotSupported; }
+
+int scratch_acquire(int, void**, hipError_t* err) {
+  *err = hipErrorNotSupported;
+  return SCRATCH_HIP_ERROR;
+}
+void scratch_release(int) {}
 
 }  // namespace fmnmf
