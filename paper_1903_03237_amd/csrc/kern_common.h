@@ -285,7 +285,11 @@ struct Batch {
   int n;
 };
 
-__device__ __forceinline__ const KArgs& batch_block(const Batch& B, Blk& blk) {
+// The context's arguments are copied out of the table once, before any
+// store, through a restrict pointer: the compiler then knows the array
+// pointers in them address global memory (global, not flat, loads and
+// stores; a flat load waits on every global load in flight).
+__device__ __forceinline__ KArgs batch_block(const Batch& B, Blk& blk) {
   const int lin = blockIdx.x;
   int i = 0;
   for (int j = 1; j < B.n; ++j)
@@ -293,7 +297,8 @@ __device__ __forceinline__ const KArgs& batch_block(const Batch& B, Blk& blk) {
   const int r = lin - B.start[i];
   blk.x = r % B.gx[i];
   blk.y = r / B.gx[i];
-  return *B.a[i];
+  const KArgs* __restrict__ pa = B.a[i];
+  return *pa;
 }
 
 // Device-side error latch (vector-memory atomic on a global word).
