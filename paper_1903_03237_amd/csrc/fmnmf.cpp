@@ -52,7 +52,6 @@ struct Layout {
   int MP, FP, TP, KP, K4, KPB, KT;
   int Sw, Sh, Sg, Sv, tw, fh, tg, tv, nll;
   size_t rb;  // bytes of one real element (FP64: 8, else 4)
-  size_t off_kdev;
   size_t off_Qi64;
   size_t off_Lam;
   size_t off_Xt, off_W, off_H, off_G, off_Wb, off_Wtb, off_Hb, off_Htb, off_Q, off_Qr, off_Qinv, off_logdet,
@@ -151,7 +150,6 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   L->off_status = take(8);
   L->off_ll = take(8);
   L->off_Yd = take((d->flags & FMNMF_WITH_DERIVED) ? F * T * MP * rb : 0);
-  L->off_kdev = take(sizeof(KArgs));
   L->total = align_up(off, 256);
 }
 
@@ -160,7 +158,7 @@ struct Ops {
   launch_fn wpass, hpass, gpass, vpass, proj, ip, logdet, qinv, mirror, norm, lampass, init_scm;
   hipError_t (*mu)(const KArgs&, int, hipStream_t);
   hipError_t (*wiener)(const KArgs&, void*, hipStream_t);
-  hipError_t (*batch)(int, const KArgs* const*, const KArgs* const*, int, hipStream_t);
+  hipError_t (*batch)(int, const KArgs* const*, int, hipStream_t);
 };
 #define FM_OPS(sfx)                                                                                       \
   Ops {                                                                                                   \
@@ -183,7 +181,6 @@ struct fmnmf_ctx {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   bool graph_tried = false;
-  KArgs* kdev = nullptr;      // device copy of a (read by batched launches)
   hipEvent_t ev = nullptr;    // joins this context's stream with a batch's stream
   int scratch_dev = -1;       // device whose scratch array is the workspace (fmnmf_init_noalloc)
 };
@@ -418,13 +415,11 @@ int enqueue_batch_iteration(fmnmf_ctx* const* cs, int count, hipStream_t s) {
   for (int k : kOrder) {
     for (auto& g : groups) {
       const KArgs* host[fmnmf::MAXB_HOST];
-      const KArgs* dev[fmnmf::MAXB_HOST];
       const int n = (int)g.idx.size();
       for (int j = 0; j < n; ++j) {
         host[j] = &cs[g.idx[j]]->a;
-        dev[j] = cs[g.idx[j]]->kdev;
       }
-      int rc = launch_check(kOps[g.prec].batch(k, host, dev, n, s), kKernelNames[k]);
+      int rc = launch_check(kOps[g.prec].batch(k, host, n, s), kKernelNames[k]);
       if (rc) return rc;
     }
   }
@@ -598,11 +593,9 @@ int init_ctx(fmnmf_ctx** out, const fmnmf_dims* d, const void* X_dev, void* ws_d
   a.fh = L.fh;
   a.tg = L.tg;
   a.tv = L.tv;
-  c->kdev = reinterpret_cast<KArgs*>(ws + L.off_kdev);
   c->scratch_dev = scratch_dev;
   // the workspace starts at zero (padding of every array, the status word)
   hipError_t e = hipMemsetAsync(ws_dev, 0, L.total, c->s);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->kdev, &c->a, sizeof(KArgs), hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess && with_event) e = hipEventCreateWithFlags(&c->ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     if (c->ev) (void)hipEventDestroy(c->ev);

@@ -5,8 +5,8 @@
 
 namespace fmnmf {
 
-// Contexts per batched launch (the device-side table size).
-constexpr int MAXB_HOST = 16;
+// Contexts per batched launch (their arguments travel by value in the launch).
+constexpr int MAXB_HOST = 12;
 
 // Bits of the device-side sticky status word.
 enum : int { ST_SINGULAR = 1, ST_NONFINITE = 2 };

@@ -270,8 +270,11 @@ __device__ __forceinline__ void wave_sync() {
 // batched launch.  A batched launch runs the same kernel for up to MAXB
 // contexts of one shape class in a single 1-D grid: context i owns linear
 // blocks [start[i], start[i+1]), laid out x-fastest over its own grid of
-// width gx[i]; its arguments are read from the device copy a[i] kept in the
-// context's workspace.
+// width gx[i]; its arguments a[i] travel by value in the launch's argument
+// block (MAXB = 12 keeps the block under 4 KiB), so, as in a plain launch,
+// the compiler knows that their array pointers address global memory (a
+// pointer it cannot place is read with flat loads, which wait on every
+// global load in flight).
 // ---------------------------------------------------------------------------
 struct Blk {
   int x, y;
@@ -279,17 +282,14 @@ struct Blk {
 
 constexpr int MAXB = MAXB_HOST;
 struct Batch {
-  const KArgs* a[MAXB];
+  KArgs a[MAXB];
   int start[MAXB + 1];
   int gx[MAXB];
   int n;
 };
+static_assert(sizeof(Batch) <= 4096, "batched launch arguments exceed 4 KiB");
 
-// The context's arguments are copied out of the table once, before any
-// store, through a restrict pointer: the compiler then knows the array
-// pointers in them address global memory (global, not flat, loads and
-// stores; a flat load waits on every global load in flight).
-__device__ __forceinline__ KArgs batch_block(const Batch& B, Blk& blk) {
+__device__ __forceinline__ const KArgs& batch_block(const Batch& B, Blk& blk) {
   const int lin = blockIdx.x;
   int i = 0;
   for (int j = 1; j < B.n; ++j)
@@ -297,8 +297,7 @@ __device__ __forceinline__ KArgs batch_block(const Batch& B, Blk& blk) {
   const int r = lin - B.start[i];
   blk.x = r % B.gx[i];
   blk.y = r / B.gx[i];
-  const KArgs* __restrict__ pa = B.a[i];
-  return *pa;
+  return B.a[i];
 }
 
 // Device-side error latch (vector-memory atomic on a global word).

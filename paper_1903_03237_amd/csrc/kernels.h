@@ -22,7 +22,7 @@ namespace fmnmf {
   hipError_t launch_init_scm_##sfx(const KArgs& a, hipStream_t s);         \
   hipError_t launch_mirror_##sfx(const KArgs& a, hipStream_t s);           \
   hipError_t launch_mu_##sfx(const KArgs& a, int which, hipStream_t s);     \
-  hipError_t launch_batch_##sfx(int kernel, const KArgs* const* host, const KArgs* const* dev, int n, hipStream_t s);
+  hipError_t launch_batch_##sfx(int kernel, const KArgs* const* host, int n, hipStream_t s);
 FM_DECLARE(f64)
 FM_DECLARE(f32)
 FM_DECLARE(bf16)

@@ -24,7 +24,7 @@ namespace fmnmf {
   hipError_t launch_init_scm_##sfx(const KArgs&, hipStream_t) { return hipErrorNotSupported; }          \
   hipError_t launch_mirror_##sfx(const KArgs&, hipStream_t) { return hipErrorNotSupported; }            \
   hipError_t launch_mu_##sfx(const KArgs&, int, hipStream_t) { return hipErrorNotSupported; }           \
-  hipError_t launch_batch_##sfx(int, const KArgs* const*, const KArgs* const*, int, hipStream_t) {      \
+  hipError_t launch_batch_##sfx(int, const KArgs* const*, int, hipStream_t) {                          \
     return hipErrorNotSupported;                                                                        \
   }
 FM_STUB(f64)
