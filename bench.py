@@ -312,8 +312,10 @@ def serving_leg(torch, n_requests, precision, iters=100):
             reqs.append(serve.Request(sp.rid, sp.arrival, X, sp.N, sp.K, init, delta, iters))
         return reqs
 
+    order = os.environ.get("FMNMF_SERVE_ORDER", "fcfs")
+    max_bins = int(os.environ.get("FMNMF_SERVE_MAX_BINS", 1_000_000))
     srv = serve.Server(precision=precision, hbm_budget=96 << 30, max_active=64, chunk=10,
-                       max_bins=int(os.environ.get("FMNMF_SERVE_MAX_BINS", 1_000_000)))
+                       max_bins=max_bins, order=order)
     print("[bench] serving: closed loop (all requests at t = 0)", file=sys.stderr, flush=True)
     closed = build(None)
     cap = serve.summary(srv.run(closed), closed)
@@ -327,6 +329,7 @@ def serving_leg(torch, n_requests, precision, iters=100):
     seq = serve.summary(serve.run_sequential(reqs, precision=precision), reqs)
     torch.cuda.synchronize()
     return {"requests": n_requests, "iters_per_request": iters, "precision": precision,
+            "admission": {"order": order, "max_bins": max_bins},
             "workload": "M in {2,4,8}, N in {2..5}, K in {8,16,32}, F=513, T ~ U{200..4000}; "
                         "crops of seeded base mixtures, seeded per-request initial states",
             "closed_loop": cap, "closed_loop_one_at_a_time": cap_seq, "arrival_rate_per_s": rate, "batched": batched, "one_at_a_time": seq,

@@ -2,7 +2,8 @@
 
 Requests (mixtures of different M, N, K and T) arrive over time.  The server
 
-* admits requests first come, first served, as soon as a slot is free, its
+* admits requests first come, first served (or least work first, order
+  "sjf"), as soon as a slot is free, its
   HBM footprint (fmnmf_footprint_bytes: mixture, workspace and separated
   output) fits the budget and the admitted work (time-frequency bins) stays
   near what fills the GPU, and keeps its mixture and parameters resident;
@@ -86,13 +87,18 @@ def footprint(req: Request, precision: str) -> int:
 class Server:
     def __init__(self, precision: str = "bf16", hbm_budget: int = 64 << 30, max_active: int = 64,
                  max_bins: int = 1_000_000, chunk: int = 10, device: str = "cuda:0",
-                 keep_outputs: bool = False):
+                 keep_outputs: bool = False, order: str = "fcfs"):
         """hbm_budget: bytes of device memory the admitted requests may hold;
         max_active: slots; max_bins: time-frequency bins (sum of F*T) admitted
         together per waiting request, about what fills the GPU: with one
         request waiting the admitted work stays near max_bins (a larger
         request runs alone), a backlog of b waiting requests allows b times
-        as much.  Admission is first come, first served."""
+        as much.  order: which arrived request is admitted next, "fcfs"
+        (first come, first served) or "sjf" (the least work, F*T*iters,
+        first; ties by arrival)."""
+        if order not in ("fcfs", "sjf"):
+            raise ValueError(f"unknown admission order {order!r}")
+        self.order = order
         self.precision = precision
         self.budget = int(hbm_budget)
         self.max_active = int(max_active)
@@ -135,24 +141,29 @@ class Server:
 
         bins = lambda r: r.X.shape[0] * r.X.shape[1]  # noqa: E731
 
+        arrived: list[Request] = []  # arrived and not admitted, in arrival order
+        work = lambda r: (bins(r) * r.iters, r.arrival, r.rid)  # noqa: E731
+
         def admit():
             nonlocal pi, used
             now = clock()
-            while pi < len(pending) and pending[pi].arrival <= now and len(active) < self.max_active:
-                fp = footprint(pending[pi], self.precision)
+            while pi < len(pending) and pending[pi].arrival <= now:
+                arrived.append(pending[pi])
+                pi += 1
+            while arrived and len(active) < self.max_active:
+                j = 0 if self.order == "fcfs" else min(range(len(arrived)), key=lambda i: work(arrived[i]))
+                r = arrived[j]
+                fp = footprint(r, self.precision)
                 load = sum(bins(s.req) for s in active)
                 # work cap, raised by the backlog of arrived requests still waiting
-                backlog = 0
-                while pi + backlog < len(pending) and pending[pi + backlog].arrival <= now:
-                    backlog += 1
-                cap = self.max_bins * backlog
-                if used + fp > self.budget or (active and load + bins(pending[pi]) > cap):
+                cap = self.max_bins * len(arrived)
+                if used + fp > self.budget or (active and load + bins(r) > cap):
                     break
-                s = self._admit(pending[pi], clock())
+                arrived.pop(j)
+                s = self._admit(r, clock())
                 active.append(s)
                 planned[s.req.rid] = 0
                 used += fp
-                pi += 1
                 if s.req.iters == 0:  # nothing to iterate: the filter of its initial state
                     retire(s)
 
@@ -192,7 +203,7 @@ class Server:
             inflight.append((ev, comp, n))
             return True
 
-        while pi < len(pending) or active:
+        while pi < len(pending) or arrived or active:
             admit()
             while len(inflight) < 2 and enqueue():
                 pass

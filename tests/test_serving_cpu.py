@@ -94,3 +94,21 @@ def test_budget_limits_the_admitted_footprint(fake):
     res = srv.run(reqs)
     assert fake.peak == 2  # 100 bytes each, budget 250
     assert all(r.loglik == -10.0 for r in res)
+
+
+def test_sjf_admits_the_least_work_first(fake):
+    """With one slot, requests that have all arrived are admitted least work
+    (F*T*iters) first under "sjf" and in arrival order under "fcfs"."""
+    reqs = [_req(0, 9), _req(1, 3), _req(2, 6), _req(3, 1)]
+
+    def admitted_order(order):
+        srv = serve.Server(precision="fp32", hbm_budget=10_000, max_active=1, chunk=2, device="cpu",
+                           max_bins=10**9, order=order)
+        res = srv.run(reqs)
+        assert all(r.error == 0 for r in res)
+        return [r.rid for r in sorted(res, key=lambda r: r.admitted)]
+
+    assert admitted_order("fcfs") == [0, 1, 2, 3]
+    assert admitted_order("sjf") == [3, 1, 2, 0]
+    with pytest.raises(ValueError):
+        serve.Server(order="lifo")
