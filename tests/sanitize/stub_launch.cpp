@@ -1,9 +1,9 @@
 // Host-only stand-ins for the kernel launchers (and the static scratch
-// lookup) of libfmnmf.so, for building
-// the C ABI's host code (fmnmf.cpp) with the address and undefined-behaviour
-// sanitizers on a machine without a GPU.  Every launcher reports failure;
-// the checks that use this build exercise only paths that return before any
-// device work.
+// lookup) of libfmnmf.so, for building the C ABI's host code (fmnmf.cpp)
+// with the address and undefined-behaviour sanitizers on a machine without a
+// GPU.  Every launcher reports failure; the checks run against the
+// instrumented library exercise only paths that return before any device
+// work.
 #include "../../paper_1903_03237_amd/csrc/kernels.h"
 #include "../../paper_1903_03237_amd/csrc/scratch.h"
 
