@@ -103,9 +103,11 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   const int nF = cdiv(d->F, 16), nT = cdiv(d->T, 16);
   // Workgroups aimed at per pass (measured at M=8, N=5, K=32, F=513,
   // T=3000 on MI355X: the best split counts lie near these totals; the G~
-  // pass stays below 512 because its FP32 form holds only two per CU).
+  // pass stays below 512 because its FP32 form holds only two per CU; the
+  // FP32 H pass, which holds its operands a step ahead, does best with two
+  // splits, 52 + 8 us for the pass and its update against 54 + 10 at four).
   // FMNMF_WG_TARGET overrides the W / H / G~ targets.
-  int tw = 660, th = 752, tg = 480, tv = 512;
+  int tw = 660, th = d->precision == FMNMF_FP32 ? std::max(376, 2 * nT) : 752, tg = 480, tv = 512;
   if (const char* e = std::getenv("FMNMF_WG_TARGET")) tw = th = tg = std::max(1, std::atoi(e));
   // FMNMF_SPLITS="w,h,g,v" fixes the number of splits per pass (0 = automatic)
   int fix[4] = {0, 0, 0, 0};
