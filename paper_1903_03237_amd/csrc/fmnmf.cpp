@@ -116,8 +116,11 @@ void make_layout(const fmnmf_dims* d, Layout* L) {
   choose_split(nF, d->T, slots_for(0, nF, tw), 64, 16, &L->Sw, &L->tw);
   choose_split(nT, d->F, slots_for(1, nT, th), 64, 16, &L->Sh, &L->fh);
   choose_split(nF, d->T, slots_for(2, nF, tg), 64, 16, &L->Sg, &L->tg);
-  // V pass: at least tv workgroups (its workgroups are 512 threads, two per CU)
-  choose_split(nF, d->T, slots_for(3, nF, cdiv(tv, nF) * nF), 32, 16, &L->Sv, &L->tv);
+  // V pass: at least tv workgroups (its workgroups are 512 threads, two per
+  // CU); at M = 8 off the FP64 path (4x4x1 form, 256 threads, two per CU) at
+  // most tv, so that the grid is resident at once
+  const bool v4 = d->M == 8 && d->precision != FMNMF_FP64;
+  choose_split(nF, d->T, slots_for(3, nF, v4 ? std::max(1, tv / nF) * nF : cdiv(tv, nF) * nF), 32, 16, &L->Sv, &L->tv);
   L->nll = cdiv(d->F, 16) * cdiv(d->T, 64);
   L->rb = d->precision == FMNMF_FP64 ? 8 : 4;
   const size_t rb = L->rb, cb = 2 * rb;
