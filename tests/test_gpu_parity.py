@@ -157,6 +157,37 @@ def test_reduced_precision_one_step(device, precision, tol_ll, tol_state, case):
     m.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_v_pass_long_frame_splits(device, precision, monkeypatch):
+    """The V pass with its frames in two splits (FMNMF_SPLITS), so that the
+    workgroups walk 29 and 28 steps of 16 frames (an odd and an even count,
+    the last step ragged), at M = 8 (on the FP32 and bf16 paths the 4x4x1
+    form), one step from an injected oracle state against the oracle's."""
+    F, T, M, N, K = 33, 900, 8, 3, 8
+    X, init, delta = synth.random_problem(F, T, M, N, K, seed=5, delta_rel=1e-8, random_q=True)
+    if precision != "fp64":
+        X = X.astype(np.complex64).astype(np.complex128)  # the oracle sees the same rounded input
+    s1 = fm.step(X, fm.State(*init), delta)
+    monkeypatch.setenv("FMNMF_SPLITS", "0,0,0,2")
+    m = _model(device, X, N, K, init, precision, delta)
+    m.set_state(s1.W, s1.H, s1.G, s1.Q)
+    m.step(1)
+    s2 = fm.step(X, s1, delta)
+    l2 = fm.loglik(X, s2, delta)
+    W, H, G, Q = m.get_state()
+    pairs = (("W", W, s2.W), ("H", H, s2.H), ("G", G, s2.G), ("Q", Q, s2.Q))
+    if precision == "fp64":
+        assert abs(m.loglik() - l2) <= 1e-10 * abs(l2)
+        for name, a, b in pairs:
+            assert_close(name, a, b, **FP64)
+    else:
+        tol_ll, tol_state = (1e-5, 2e-3) if precision == "fp32" else (5e-4, 5e-2)
+        assert abs(m.loglik() - l2) <= tol_ll * max(abs(l2), F * T * M), (m.loglik(), l2)
+        for name, a, b in pairs:
+            assert _rel(a, b) < tol_state, (name, _rel(a, b))
+    m.close()
+
+
 @pytest.mark.parametrize("M", [4, 5])
 def test_separate_into_8_byte_aligned_output(device, M):
     """The filter writes 16-byte vectors only to 16-byte aligned outputs with
