@@ -131,7 +131,8 @@ def test_fp64_deterministic(device):
 # average out; the full-size errors are reported by the precision study.
 @pytest.mark.parametrize("precision,tol_ll,tol_state", [("fp32", 1e-5, 2e-3), ("bf16", 5e-4, 5e-2)])
 @pytest.mark.parametrize("case", [(33, 90, 4, 3, 16), (50, 200, 8, 5, 32), (21, 37, 3, 2, 5),
-                                  (65, 96, 8, 6, 64), (40, 80, 7, 8, 48)],
+                                  (65, 96, 8, 6, 64), (40, 80, 7, 8, 48), (21, 45, 8, 2, 5),
+                                  (33, 60, 8, 3, 16), (40, 80, 8, 7, 48)],
                          ids=lambda c: "F%dT%dM%dN%dK%d" % c)
 def test_reduced_precision_one_step(device, precision, tol_ll, tol_state, case):
     F, T, M, N, K = case
